@@ -1,0 +1,536 @@
+// aca_api.hip -- C-ABI of libaca (declared in include/aca.h).
+//
+// Host side of the conservative simulation: argument checks, the flip
+// thresholds, the tile plan, and the launch loop of aca_advance.  The loop
+// advances every tile region once per launch from a snapshot of the whole
+// lattice (double buffer: the caller's state and a copy in scratch), reads
+// back the per-launch counters, and stops when no owned cell has an arrival
+// before the horizon.  A launch that applies nothing while arrivals are due
+// is reported as ACA_ENOPROGRESS: the cell holding the globally earliest
+// arrival always sees current neighbours at load time and must be able to
+// move (the deadlock-freedom argument of Fig. 3.1 and Fig. 3.4).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <chrono>
+#include <cstdio>
+#include <string>
+
+#include "../../include/aca.h"
+#include "aca_internal.h"
+
+#define ACA_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace aca {
+hipError_t set_visit_lds_limit(size_t bytes);
+}
+
+namespace {
+
+thread_local std::string g_error;
+
+aca_status fail(aca_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+aca_status fail(aca_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(ACA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct ScratchLayout {
+    size_t s_off, t_off, n_off, ctr_off, total;
+};
+
+ScratchLayout scratch_layout(uint64_t n)
+{
+    ScratchLayout l;
+    l.s_off = 0;
+    l.t_off = align_up(l.s_off + n);
+    l.n_off = align_up(l.t_off + 8 * n);
+    l.ctr_off = align_up(l.n_off + 4 * n);
+    l.total = l.ctr_off + kAlign;
+    return l;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+aca_status check_params(const aca_params *p, uint64_t *n_out)
+{
+    if (!p) return fail(ACA_EINVAL, "params is NULL");
+    if (p->struct_size != sizeof(aca_params))
+        return fail(ACA_EINVAL, "params.struct_size %u != %zu", p->struct_size,
+                    sizeof(aca_params));
+    if (p->dim < 1 || p->dim > 3) return fail(ACA_EINVAL, "dim %d not in 1..3", p->dim);
+    uint64_t n = 1;
+    for (int d = 0; d < p->dim; ++d) {
+        if (p->L[d] < 2) return fail(ACA_EINVAL, "L[%d] = %d < 2", d, p->L[d]);
+        n *= (uint64_t)p->L[d];
+        if (n >= (1ull << 32)) return fail(ACA_EINVAL, "lattice has >= 2^32 cells");
+    }
+    if (!is_finite(p->J) || !is_finite(p->h)) return fail(ACA_EINVAL, "J and h must be finite");
+    if (!is_finite(p->beta) || p->beta < 0.0)
+        return fail(ACA_EINVAL, "beta must be finite and >= 0");
+    if (!is_finite(p->rate) || !(p->rate > 0.0))
+        return fail(ACA_EINVAL, "rate must be finite and > 0");
+    if (p->rule != ACA_GLAUBER && p->rule != ACA_METROPOLIS)
+        return fail(ACA_EINVAL, "unknown rule %d", p->rule);
+    if (p->init < ACA_INIT_RANDOM || p->init > ACA_INIT_MINUS)
+        return fail(ACA_EINVAL, "unknown init %d", p->init);
+    if (n_out) *n_out = n;
+    return ACA_OK;
+}
+
+// Flip table of the appendix program generalised to z = 2 dim slots:
+// entry (sum + z)/2 + (z+1)(s+1)/2 holds floor(p 2^32), 2^32 when p >= 1.
+int build_thresholds(const aca_params *p, uint64_t *thr)
+{
+    const int z = 2 * p->dim;
+    for (int spin = -1; spin <= 1; spin += 2) {
+        for (int sum = -z; sum <= z; sum += 2) {
+            const double js = p->J * (double)sum;
+            const double field = js + p->h;
+            const double dE = 2.0 * ((double)spin * field);
+            double prob;
+            if (p->rule == ACA_GLAUBER) {
+                const double x = exp(p->beta * dE);
+                prob = 1.0 / (1.0 + x);
+            } else {
+                prob = (dE <= 0.0) ? 1.0 : exp(-(p->beta * dE));
+            }
+            const uint64_t v = (prob >= 1.0) ? (1ull << 32)
+                                              : (uint64_t)floor(prob * 4294967296.0);
+            thr[(sum + z) / 2 + (z + 1) * (spin + 1) / 2] = v;
+        }
+    }
+    return 2 * (z + 1);
+}
+
+}  // namespace
+
+struct aca_lattice {
+    aca_params p;
+    uint64_t n;
+    int8_t *s[2];
+    double *t[2];
+    uint32_t *cnt[2];
+    unsigned long long *counters;   // device, in scratch
+    int cur;                        // which copy holds the current state
+    bool initialized;
+    double last_T;
+    aca_tuning tun;                 // as requested (0 / -1 = automatic)
+    aca_stats stats;
+    uint64_t thr[14];
+    int device;
+    hipEvent_t ev_start, ev_stop;
+};
+
+namespace {
+
+struct Plan {
+    aca::VisitArgs a;
+    int block;
+    size_t lds;
+};
+
+// Automatic schedule knobs; every choice gives the same result.
+void auto_tuning(const aca_params &p, aca_tuning *t)
+{
+    if (p.dim == 1) {
+        t->tile[0] = 8192; t->ghost[0] = 64;
+        t->max_sweeps = 64; t->block = 256;
+    } else if (p.dim == 2) {
+        t->tile[0] = 64; t->tile[1] = 64;
+        t->ghost[0] = 4; t->ghost[1] = 4;
+        t->max_sweeps = 32; t->block = 512;
+    } else {
+        t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 8;
+        t->ghost[0] = 2; t->ghost[1] = 2; t->ghost[2] = 2;
+        t->max_sweeps = 24; t->block = 512;
+    }
+}
+
+aca_status make_plan(const aca_lattice *lat, double T, int in, Plan *plan)
+{
+    const aca_params &p = lat->p;
+    aca_tuning t;
+    memset(&t, 0, sizeof t);
+    t.ghost[0] = t.ghost[1] = t.ghost[2] = -1;
+    auto_tuning(p, &t);
+    for (int d = 0; d < 3; ++d) {
+        if (lat->tun.tile[d] > 0) t.tile[d] = lat->tun.tile[d];
+        if (lat->tun.ghost[d] >= 0) t.ghost[d] = lat->tun.ghost[d];
+    }
+    if (lat->tun.max_sweeps > 0) t.max_sweeps = lat->tun.max_sweeps;
+    if (lat->tun.block > 0) t.block = lat->tun.block;
+    if (t.block % 64 != 0 || t.block < 64 || t.block > 1024)
+        return fail(ACA_EINVAL, "block %d must be a multiple of 64 in [64, 1024]", t.block);
+
+    aca::VisitArgs &a = plan->a;
+    memset(&a, 0, sizeof a);
+    for (int d = 0; d < 3; ++d) {
+        if (d < p.dim) {
+            const int L = p.L[d];
+            a.L[d] = L;
+            if (t.tile[d] >= L) {
+                a.span[d] = 1; a.tile[d] = L; a.ntiles[d] = 1; a.ghost[d] = 0;
+            } else {
+                a.span[d] = 0;
+                a.tile[d] = t.tile[d];
+                a.ntiles[d] = (L + t.tile[d] - 1) / t.tile[d];
+                // keep the simulated region within one period of the lattice
+                a.ghost[d] = std::max(0, std::min(t.ghost[d], (L - t.tile[d]) / 2));
+            }
+        } else {
+            a.L[d] = 1; a.tile[d] = 1; a.ntiles[d] = 1; a.ghost[d] = 0; a.span[d] = 1;
+        }
+    }
+    a.max_sweeps = t.max_sweeps;
+    a.key_lo = (uint32_t)p.seed;
+    a.key_hi = (uint32_t)(p.seed >> 32);
+    a.rate = p.rate;
+    a.unit_rate = p.rate == 1.0 ? 1 : 0;
+    uint64_t hb;
+    memcpy(&hb, &T, sizeof hb);
+    a.horizon_bits = hb;
+    const int out = 1 - in;
+    a.s_in = lat->s[in]; a.t_in = lat->t[in]; a.n_in = lat->cnt[in];
+    a.s_out = lat->s[out]; a.t_out = lat->t[out]; a.n_out = lat->cnt[out];
+    a.counters = lat->counters;
+    memcpy(a.thr, lat->thr, sizeof a.thr);
+    plan->block = t.block;
+    plan->lds = aca::visit_lds_bytes(p.dim, a, t.block);
+    int dev_lds = 0;
+    HIP_TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                  lat->device));
+    if (plan->lds > (size_t)dev_lds)
+        return fail(ACA_EINVAL, "tile region needs %zu B of LDS, device has %d B",
+                    plan->lds, dev_lds);
+    uint64_t tiles = (uint64_t)a.ntiles[0] * a.ntiles[1] * a.ntiles[2];
+    if (tiles > 0x7FFFFFFFull) return fail(ACA_EINVAL, "too many tiles");
+    return ACA_OK;
+}
+
+// Bytes one launch must move: for each tile, (spin, time) of its whole region
+// box and the counts of its simulated cells in, (spin, time, count) of its own
+// cells out.
+uint64_t launch_region_bytes(int dim, const aca::VisitArgs &a)
+{
+    uint64_t total = 0;
+    const int nt[3] = {a.ntiles[0], a.ntiles[1], a.ntiles[2]};
+    // tiles along each direction come in at most two widths (the last is ragged)
+    for (int ix = 0; ix < 2; ++ix)
+        for (int iy = 0; iy < 2; ++iy)
+            for (int iz = 0; iz < 2; ++iz) {
+                const int pick[3] = {ix, iy, iz};
+                uint64_t count = 1, box = 1, inner = 1, own = 1;
+                bool any = true;
+                for (int d = 0; d < 3; ++d) {
+                    const int full = (a.L[d] / a.tile[d] == nt[d]) ? nt[d] : nt[d] - 1;
+                    const int m = pick[d] ? nt[d] - full : full;
+                    if (m <= 0) { any = false; break; }
+                    const int w = pick[d] ? a.L[d] - full * a.tile[d] : a.tile[d];
+                    count *= (uint64_t)m;
+                    own *= (uint64_t)w;
+                    const int rin = a.span[d] ? a.L[d] : w + 2 * a.ghost[d];
+                    inner *= (uint64_t)rin;
+                    box *= (uint64_t)(rin + (a.span[d] ? 0 : 2));
+                    (void)dim;
+                }
+                if (any) total += count * (9 * box + 4 * inner + 13 * own);
+            }
+    return total;
+}
+
+}  // namespace
+
+ACA_EXPORT uint32_t aca_abi_version(void) { return ACA_ABI_VERSION; }
+
+ACA_EXPORT const char *aca_last_error(void) { return g_error.c_str(); }
+
+ACA_EXPORT aca_status aca_thresholds(const aca_params *p, uint64_t *out, int32_t cap,
+                                     int32_t *count)
+{
+    aca_status st = check_params(p, nullptr);
+    if (st != ACA_OK) return st;
+    if (!out) return fail(ACA_EINVAL, "out is NULL");
+    const int need = 2 * (2 * p->dim + 1);
+    if (cap < need) return fail(ACA_EINVAL, "cap %d < %d entries", cap, need);
+    uint64_t thr[14];
+    build_thresholds(p, thr);
+    memcpy(out, thr, sizeof(uint64_t) * need);
+    if (count) *count = need;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_query(const aca_params *p, uint64_t *n_cells,
+                                uint64_t *scratch_bytes)
+{
+    uint64_t n = 0;
+    aca_status st = check_params(p, &n);
+    if (st != ACA_OK) return st;
+    if (n_cells) *n_cells = n;
+    if (scratch_bytes) *scratch_bytes = scratch_layout(n).total;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_time,
+                                 uint32_t *d_count, void *d_scratch,
+                                 uint64_t scratch_bytes, aca_lattice **out)
+{
+    uint64_t n = 0;
+    aca_status st = check_params(p, &n);
+    if (st != ACA_OK) return st;
+    if (!out) return fail(ACA_EINVAL, "out is NULL");
+    if (!d_spin || !d_time || !d_count || !d_scratch)
+        return fail(ACA_EINVAL, "a device buffer is NULL");
+    const void *bufs[4] = {d_spin, d_time, d_count, d_scratch};
+    for (const void *b : bufs)
+        if (((uintptr_t)b) % kAlign != 0)
+            return fail(ACA_EINVAL, "device buffers must be %zu-byte aligned", kAlign);
+    const ScratchLayout sl = scratch_layout(n);
+    if (scratch_bytes < sl.total)
+        return fail(ACA_ENOMEM, "scratch has %llu bytes, needs %zu",
+                    (unsigned long long)scratch_bytes, sl.total);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    aca_lattice *lat = new (std::nothrow) aca_lattice();
+    if (!lat) return fail(ACA_ENOMEM, "host allocation failed");
+    lat->p = *p;
+    lat->n = n;
+    char *sc = static_cast<char *>(d_scratch);
+    lat->s[0] = d_spin;
+    lat->t[0] = d_time;
+    lat->cnt[0] = d_count;
+    lat->s[1] = reinterpret_cast<int8_t *>(sc + sl.s_off);
+    lat->t[1] = reinterpret_cast<double *>(sc + sl.t_off);
+    lat->cnt[1] = reinterpret_cast<uint32_t *>(sc + sl.n_off);
+    lat->counters = reinterpret_cast<unsigned long long *>(sc + sl.ctr_off);
+    lat->cur = 0;
+    lat->initialized = false;
+    lat->last_T = 0.0;
+    memset(&lat->tun, 0, sizeof lat->tun);
+    lat->tun.struct_size = sizeof(aca_tuning);
+    lat->tun.ghost[0] = lat->tun.ghost[1] = lat->tun.ghost[2] = -1;
+    memset(&lat->stats, 0, sizeof lat->stats);
+    lat->stats.struct_size = sizeof(aca_stats);
+    build_thresholds(p, lat->thr);
+    lat->device = dev;
+    if (hipEventCreate(&lat->ev_start) != hipSuccess ||
+        hipEventCreate(&lat->ev_stop) != hipSuccess) {
+        delete lat;
+        return fail(ACA_EDEVICE, "hipEventCreate failed");
+    }
+    *out = lat;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_set_tuning(aca_lattice *lat, const aca_tuning *t)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    aca_tuning v;
+    memset(&v, 0, sizeof v);
+    v.struct_size = sizeof v;
+    v.ghost[0] = v.ghost[1] = v.ghost[2] = -1;
+    if (t) {
+        if (t->struct_size != sizeof(aca_tuning))
+            return fail(ACA_EINVAL, "tuning.struct_size mismatch");
+        for (int d = 0; d < 3; ++d)
+            if (t->tile[d] < 0) return fail(ACA_EINVAL, "tile[%d] < 0", d);
+        if (t->max_sweeps < 0) return fail(ACA_EINVAL, "max_sweeps < 0");
+        if (t->block != 0 && (t->block % 64 != 0 || t->block > 1024))
+            return fail(ACA_EINVAL, "block must be a multiple of 64 up to 1024");
+        v = *t;
+    }
+    lat->tun = v;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_get_tuning(const aca_lattice *lat, aca_tuning *out)
+{
+    if (!lat || !out) return fail(ACA_EINVAL, "NULL argument");
+    Plan plan;
+    aca_status st = make_plan(lat, 1.0, 0, &plan);
+    if (st != ACA_OK) return st;
+    memset(out, 0, sizeof *out);
+    out->struct_size = sizeof *out;
+    for (int d = 0; d < 3; ++d) {
+        out->tile[d] = plan.a.tile[d];
+        out->ghost[d] = plan.a.ghost[d];
+    }
+    out->max_sweeps = plan.a.max_sweeps;
+    out->block = plan.block;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_init(aca_lattice *lat, void *stream)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(aca::launch_init(lat->p.dim, lat->p.L, lat->n, (uint32_t)lat->p.seed,
+                             (uint32_t)(lat->p.seed >> 32), lat->p.rate, lat->p.init,
+                             lat->s[0], lat->t[0], lat->cnt[0], s));
+    lat->cur = 0;
+    lat->initialized = true;
+    lat->last_T = 0.0;
+    memset(&lat->stats, 0, sizeof lat->stats);
+    lat->stats.struct_size = sizeof(aca_stats);
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_resume(aca_lattice *lat, double T_done)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (!is_finite(T_done) || T_done < 0.0)
+        return fail(ACA_EINVAL, "T_done must be finite and >= 0");
+    lat->cur = 0;
+    lat->initialized = true;
+    lat->last_T = T_done;
+    memset(&lat->stats, 0, sizeof lat->stats);
+    lat->stats.struct_size = sizeof(aca_stats);
+    lat->stats.last_T = T_done;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (!lat->initialized) return fail(ACA_ESTATE, "aca_init (or aca_resume) first");
+    if (!is_finite(T)) return fail(ACA_EINVAL, "horizon must be finite");
+    if (T < lat->last_T)
+        return fail(ACA_EINVAL, "horizon %.17g is before the last one %.17g", T,
+                    lat->last_T);
+    if (T == lat->last_T || T <= 0.0) {
+        lat->last_T = std::max(lat->last_T, T);
+        return ACA_OK;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan plan;
+    aca_status st = make_plan(lat, T, lat->cur, &plan);
+    if (st != ACA_OK) return st;
+    if (plan.lds > 64 * 1024) HIP_TRY(aca::set_visit_lds_limit(plan.lds));
+    unsigned long long host_ctr[aca::kNumCounters];
+    const uint64_t tiles = (uint64_t)plan.a.ntiles[0] * plan.a.ntiles[1] * plan.a.ntiles[2];
+    const uint64_t bytes_per_launch = launch_region_bytes(lat->p.dim, plan.a);
+    // Safety net: every launch applies at least one arrival, so the loop ends;
+    // this bound only turns a pathological schedule into an error.
+    const uint64_t max_launches = 100000;
+    for (uint64_t launch = 0;; ++launch) {
+        if (launch >= max_launches)
+            return fail(ACA_ENOPROGRESS, "horizon not reached after %llu launches",
+                        (unsigned long long)launch);
+        const int in = lat->cur, out = 1 - in;
+        plan.a.s_in = lat->s[in]; plan.a.t_in = lat->t[in]; plan.a.n_in = lat->cnt[in];
+        plan.a.s_out = lat->s[out]; plan.a.t_out = lat->t[out]; plan.a.n_out = lat->cnt[out];
+        HIP_TRY(hipMemsetAsync(lat->counters, 0, sizeof host_ctr, s));
+        HIP_TRY(hipEventRecord(lat->ev_start, s));
+        HIP_TRY(aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
+        HIP_TRY(hipEventRecord(lat->ev_stop, s));
+        HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, sizeof host_ctr,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float kms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&kms, lat->ev_start, lat->ev_stop));
+        lat->cur = out;
+        aca_stats &S = lat->stats;
+        S.kernel_ms += kms;
+        S.region_bytes += bytes_per_launch;
+        S.launches += 1;
+        S.visits += tiles;
+        S.events += host_ctr[aca::kEvents];
+        S.flips += host_ctr[aca::kFlips];
+        S.ghost_events += host_ctr[aca::kGhostEvents];
+        S.sweeps += host_ctr[aca::kSweeps];
+        S.cell_checks += host_ctr[aca::kChecks];
+        if (host_ctr[aca::kLiveTiles] == 0) break;
+        if (host_ctr[aca::kEvents] + host_ctr[aca::kGhostEvents] == 0)
+            return fail(ACA_ENOPROGRESS, "a launch applied no arrival while %llu tiles "
+                        "still had arrivals before the horizon",
+                        (unsigned long long)host_ctr[aca::kLiveTiles]);
+    }
+    if (lat->cur != 0) {
+        HIP_TRY(hipMemcpyAsync(lat->s[0], lat->s[1], lat->n, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(lat->t[0], lat->t[1], 8 * lat->n, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(lat->cnt[0], lat->cnt[1], 4 * lat->n,
+                               hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        lat->cur = 0;
+    }
+    lat->last_T = T;
+    lat->stats.last_T = T;
+    lat->stats.device_ms +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_get_stats(const aca_lattice *lat, aca_stats *out)
+{
+    if (!lat || !out) return fail(ACA_EINVAL, "NULL argument");
+    *out = lat->stats;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
+                               uint32_t *h_count, void *stream)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int c = lat->cur;
+    if (h_spin) HIP_TRY(hipMemcpyAsync(h_spin, lat->s[c], lat->n, hipMemcpyDeviceToHost, s));
+    if (h_time)
+        HIP_TRY(hipMemcpyAsync(h_time, lat->t[c], 8 * lat->n, hipMemcpyDeviceToHost, s));
+    if (h_count)
+        HIP_TRY(hipMemcpyAsync(h_count, lat->cnt[c], 4 * lat->n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_destroy(aca_lattice *lat)
+{
+    if (lat) {
+        hipEventDestroy(lat->ev_start);
+        hipEventDestroy(lat->ev_stop);
+    }
+    delete lat;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_philox(const uint32_t *d_ctr, uint64_t seed, uint32_t *d_out,
+                                 uint64_t count, void *stream)
+{
+    if (count == 0) return ACA_OK;
+    if (!d_ctr || !d_out) return fail(ACA_EINVAL, "NULL buffer");
+    HIP_TRY(aca::launch_philox(d_ctr, seed, d_out, count, static_cast<hipStream_t>(stream)));
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_neg_log(const uint64_t *d_w, double *d_out, uint64_t count,
+                                  void *stream)
+{
+    if (count == 0) return ACA_OK;
+    if (!d_w || !d_out) return fail(ACA_EINVAL, "NULL buffer");
+    HIP_TRY(aca::launch_neg_log(d_w, d_out, count, static_cast<hipStream_t>(stream)));
+    return ACA_OK;
+}

@@ -1,0 +1,62 @@
+// aca_internal.h -- launch interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aca {
+
+// Per-launch counters in device scratch (64-bit words).
+enum Counter : int {
+    kEvents = 0,        // arrivals applied to owned cells
+    kFlips = 1,         // of which reversed the spin
+    kGhostEvents = 2,   // arrivals applied to ghost copies (discarded)
+    kLiveTiles = 3,     // tiles with an owned cell still before the horizon
+    kSweeps = 4,        // sweeps summed over tile visits
+    kChecks = 5,        // enabling tests evaluated
+    kNumCounters = 8
+};
+
+// Everything a tile visit needs.  One workgroup simulates one tile region:
+// the tile's own cells, `ghost` extra cells on each side of every direction
+// the tile does not span, and a frozen one-cell ring around that.  Along a
+// direction the tile spans (tile side >= lattice side) the region is the
+// whole periodic side and its neighbours wrap inside the region.
+struct VisitArgs {
+    int32_t L[3];
+    int32_t tile[3];
+    int32_t ntiles[3];
+    int32_t ghost[3];
+    int32_t span[3];
+    int32_t max_sweeps;
+    uint32_t key_lo, key_hi;
+    int32_t unit_rate;
+    double rate;
+    uint64_t horizon_bits;     // bit pattern of the horizon T > 0
+    const int8_t *s_in;
+    const double *t_in;
+    const uint32_t *n_in;
+    int8_t *s_out;
+    double *t_out;
+    uint32_t *n_out;
+    unsigned long long *counters;
+    uint64_t thr[14];
+};
+
+// Bytes of dynamic LDS a visit needs for the largest region of this plan.
+size_t visit_lds_bytes(int dim, const VisitArgs &a, int block);
+
+hipError_t launch_init(int dim, const int32_t *L, uint64_t n_cells, uint32_t key_lo,
+                       uint32_t key_hi, double rate, int init, int8_t *s, double *t,
+                       uint32_t *n, hipStream_t stream);
+
+hipError_t launch_visit(int dim, const VisitArgs &a, int block, size_t lds,
+                        hipStream_t stream);
+
+hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out,
+                         uint64_t count, hipStream_t stream);
+
+hipError_t launch_neg_log(const uint64_t *w, double *out, uint64_t count,
+                          hipStream_t stream);
+
+}  // namespace aca

@@ -1,0 +1,108 @@
+"""The C-ABI library without a GPU: it loads, exports every function include/aca.h
+declares, validates arguments, and its host-side flip thresholds equal the
+oracle's (independent implementations of the appendix program's table)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0502039_amd import aca, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "aca.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aca_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_surface():
+    names = declared_functions()
+    assert names == sorted(aca.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = aca.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = os.popen(f"nm -D --defined-only {aca.LIB_PATH}").read()
+    exported = set(re.findall(r"\bT (aca_[a-z0-9_]+)", out))
+    assert set(declared_functions()) <= exported
+    # nothing else with the public prefix leaks out
+    assert exported == set(declared_functions())
+
+
+def test_abi_version():
+    assert aca.abi_version() == 1
+
+
+@pytest.mark.parametrize("params", workloads.small_cases()
+                         + [workloads.square_4096(), workloads.cubic_256()]
+                         + workloads.batch_512()[:40])
+def test_thresholds_equal_oracle(params):
+    lib_thr = aca.thresholds(params)
+    ora_thr = oracle.thresholds(params["dim"], params["J"], params["h"], params["beta"],
+                                params["rule"])
+    assert np.array_equal(lib_thr, ora_thr)
+
+
+def test_thresholds_equal_oracle_random():
+    rng = np.random.default_rng(99)
+    for _ in range(300):
+        dim = int(rng.integers(1, 4))
+        p = workloads.lattice(dim, [4] * dim, float(rng.uniform(0, 3)),
+                              "glauber" if rng.uniform() < 0.5 else "metropolis",
+                              J=float(rng.normal()), h=float(rng.normal()))
+        assert np.array_equal(aca.thresholds(p), oracle.thresholds(
+            dim, p["J"], p["h"], p["beta"], p["rule"]))
+
+
+def test_query_sizes():
+    n, scratch = aca.query(workloads.square_4096())
+    assert n == 4096 * 4096
+    assert scratch >= 13 * n
+    n, _ = aca.query(workloads.lattice(1, (7,), 0.1))
+    assert n == 7
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=0), dict(dim=4), dict(L=[1, 5]), dict(L=[70000, 70000]),
+    dict(beta=-0.1), dict(beta=float("nan")), dict(beta=float("inf")),
+    dict(rate=0.0), dict(rate=-1.0), dict(J=float("inf")), dict(h=float("nan")),
+])
+def test_invalid_params_rejected(bad):
+    p = workloads.lattice(2, (8, 8), 0.3)
+    p.update(bad)
+    with pytest.raises(aca.AcaError) as e:
+        aca.query(p)
+    assert e.value.code == aca.ACA_EINVAL
+    assert aca.load().aca_last_error()
+
+
+def test_struct_size_checked():
+    lib = aca.load()
+    p = aca.make_params(workloads.lattice(2, (8, 8), 0.3))
+    p.struct_size = 12
+    n = ctypes.c_uint64()
+    assert lib.aca_query(ctypes.byref(p), ctypes.byref(n), None) == aca.ACA_EINVAL
+
+
+def test_null_arguments_rejected():
+    lib = aca.load()
+    assert lib.aca_query(None, None, None) == aca.ACA_EINVAL
+    assert lib.aca_advance(None, 1.0, None) == aca.ACA_EINVAL
+    assert lib.aca_init(None, None) == aca.ACA_EINVAL
+    p = aca.make_params(workloads.lattice(2, (8, 8), 0.3))
+    h = ctypes.c_void_p()
+    assert lib.aca_create(ctypes.byref(p), None, None, None, None, 0,
+                          ctypes.byref(h)) == aca.ACA_EINVAL
+    # misaligned buffers are refused before any device work
+    assert lib.aca_create(ctypes.byref(p), 8, 256, 512, 768, 1 << 20,
+                          ctypes.byref(h)) == aca.ACA_EINVAL
+    # scratch too small
+    assert lib.aca_create(ctypes.byref(p), 256, 512, 768, 1024, 16,
+                          ctypes.byref(h)) == aca.ACA_ENOMEM
