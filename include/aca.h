@@ -91,16 +91,17 @@ typedef struct aca_stats {
     uint64_t launches;      /* visit-kernel launches */
     uint64_t visits;        /* workgroup tile visits */
     uint64_t sweeps;        /* tile sweeps summed over visits */
-    uint64_t events;        /* arrivals applied (spin-updates), owned cells */
-    uint64_t flips;         /* of which reversed the spin */
-    uint64_t ghost_events;  /* arrivals applied to ghost copies, discarded */
+    uint64_t events;        /* arrivals applied (spin-updates), exact */
+    uint64_t flips;         /* of which reversed the spin, exact */
+    uint64_t ghost_events;  /* arrivals applied to ghost copies in their
+                               region (redundant work; some are merged) */
     uint64_t cell_checks;   /* enabling tests evaluated */
     double last_T;          /* horizon reached so far */
     double device_ms;       /* time spent inside aca_advance (wall, ms) */
     double kernel_ms;       /* visit-kernel time, HIP events on the stream (ms) */
-    uint64_t region_bytes;  /* bytes the visit kernels must move: region
-                               (spin, time) + simulated counts in, owned
-                               (spin, time, count) out, summed over launches */
+    uint64_t region_bytes;  /* bytes the visit kernels must move: 16 B per
+                               region cell in, 16 B per owned cell out,
+                               summed over launches */
 } aca_stats;
 
 typedef struct aca_lattice aca_lattice;   /* opaque host handle */
@@ -116,7 +117,8 @@ aca_status aca_thresholds(const aca_params *p, uint64_t *out, int32_t cap,
                           int32_t *count);
 
 /* Sizes for p: number of cells, and bytes of device scratch the caller must
- * provide to aca_create (a second copy of the state plus counters). */
+ * provide to aca_create (two working snapshots of 16 bytes per cell plus
+ * counters; 32 N + 256 bytes). */
 aca_status aca_query(const aca_params *p, uint64_t *n_cells,
                      uint64_t *scratch_bytes);
 

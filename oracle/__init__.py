@@ -84,6 +84,9 @@ def lib() -> ctypes.CDLL:
             L.oracle_run_tiled.argtypes = [i32, P, f64, f64, f64, f64, i32, u64,
                                            f64, P, i64, i64, P, P, P, P, P]
             L.oracle_run_tiled.restype = i64
+            L.oracle_run_ghost_merge.argtypes = [i32, P, f64, f64, f64, f64, i32, u64,
+                                                 f64, P, P, i64, i32, i64, P, P, P, P, P]
+            L.oracle_run_ghost_merge.restype = i64
             _LIB = L
     return _LIB
 
@@ -227,3 +230,24 @@ def run_tiled(params, T: float, s, t, n, tile, max_rounds: int = 1 << 30,
     if ev < 0:
         raise ValueError("bad lattice parameters")
     return int(ev), int(flips.value), int(stats[0]), int(stats[1]), int(stats[2])
+
+
+def run_ghost_merge(params, T: float, s, t, n, tile, ghost, max_rounds: int = 1 << 30,
+                    merge_ghosts: bool = True, max_launches: int = 1 << 40):
+    """The GPU library's launch schedule (tiles + ghost zones against one snapshot,
+    copies merged by most arrivals applied).  Returns (events, launches, rounds)."""
+    dims = _dims(params)
+    tl = np.asarray(list(tile) + [1] * (3 - len(tile)), dtype=np.int32)[:3]
+    gh = np.asarray(list(ghost) + [0] * (3 - len(ghost)), dtype=np.int32)[:3]
+    stats = np.zeros(2, dtype=np.int64)
+    flips = ctypes.c_uint64(0)
+    ev = lib().oracle_run_ghost_merge(int(params["dim"]), _p(dims),
+                                      float(params.get("J", 1.0)), float(params.get("h", 0.0)),
+                                      float(params["beta"]), float(params.get("rate", 1.0)),
+                                      RULES[params["rule"]], int(params["seed"]), float(T),
+                                      _p(tl), _p(gh), int(max_rounds), int(bool(merge_ghosts)),
+                                      int(max_launches), _p(s), _p(t), _p(n), _p(stats),
+                                      ctypes.byref(flips))
+    if ev < 0:
+        raise ValueError("bad lattice parameters")
+    return int(ev), int(stats[0]), int(stats[1])

@@ -275,3 +275,158 @@ OAPI int64_t oracle_run_tiled(int dim, const int32_t *L, double J, double h,
     if (flips_out) *flips_out = flips;
     return events;
 }
+
+/*
+ * oracle_run_ghost_merge: the GPU library's launch schedule, on the CPU.
+ *
+ * Every launch visits every tile against the same snapshot X of the
+ * lattice.  A tile's region is its own cells plus `ghost` cells on each side
+ * of every direction it does not span, surrounded by a frozen one-cell ring
+ * (copies from X).  The region runs synchronous rounds (at most max_rounds)
+ * until no cell is enabled.  Then every simulated copy -- owned or ghost --
+ * is merged into the next snapshot Y by keeping, per cell, the copy with the
+ * most arrivals applied.  All copies are prefixes of the one trajectory, so
+ * the most advanced one is correct, and the merged record is a consistent
+ * cut: an arrival kept in Y was applied while every neighbour copy in its
+ * region had all earlier arrivals applied, and Y holds at least that much of
+ * each neighbour.  With merge_ghosts = 0 only owned cells are written back,
+ * which does NOT give a consistent cut (a ghost copy can run ahead of the
+ * owner's copy); that variant exists to demonstrate the difference.
+ */
+OAPI int64_t oracle_run_ghost_merge(int dim, const int32_t *L, double J, double h,
+                                    double beta, double rate, int rule,
+                                    uint64_t seed, double T, const int32_t *tile,
+                                    const int32_t *ghost, int64_t max_rounds,
+                                    int merge_ghosts, int64_t max_launches,
+                                    int8_t *s, double *t, uint32_t *n,
+                                    int64_t *stats /* [launches, rounds] */,
+                                    uint64_t *flips_out)
+{
+    sgeom g;
+    if (make_sgeom(dim, L, &g) != 0 || !(rate > 0.0) || max_rounds < 1) return -1;
+    uint64_t thr[14];
+    oracle_thresholds(dim, J, h, beta, rule, thr);
+    int64_t w[3], cnt[3], gw[3], span[3];
+    int64_t ntiles = 1;
+    for (int d = 0; d < 3; ++d) {
+        w[d] = (d < dim) ? tile[d] : 1;
+        if (w[d] < 1) return -1;
+        span[d] = w[d] >= g.L[d];
+        if (span[d]) w[d] = g.L[d];
+        cnt[d] = (g.L[d] + w[d] - 1) / w[d];
+        gw[d] = span[d] ? 0 : ghost[d];
+        if (!span[d] && gw[d] > (g.L[d] - w[d]) / 2) gw[d] = (g.L[d] - w[d]) / 2;
+        if (gw[d] < 0) gw[d] = 0;
+        ntiles *= cnt[d];
+    }
+    int64_t cap = 1;
+    for (int d = 0; d < 3; ++d) cap *= (span[d] ? g.L[d] : w[d] + 2 * gw[d] + 2);
+    /* region-local copies: global index, spin, time, count, and whether the
+     * cell is simulated (inner) or a frozen ring copy */
+    int64_t *gi = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    int8_t *ls = (int8_t *)malloc((size_t)cap);
+    double *lt = (double *)malloc((size_t)cap * sizeof(double));
+    uint32_t *ln = (uint32_t *)malloc((size_t)cap * sizeof(uint32_t));
+    uint8_t *inner = (uint8_t *)malloc((size_t)cap);
+    uint8_t *own = (uint8_t *)malloc((size_t)cap);
+    int64_t *nbr = (int64_t *)malloc((size_t)cap * 6 * sizeof(int64_t));
+    int64_t *en = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    int *sums = (int *)malloc((size_t)cap * sizeof(int));
+    int8_t *ys = (int8_t *)malloc((size_t)g.n);
+    double *yt = (double *)malloc((size_t)g.n * sizeof(double));
+    uint32_t *yn = (uint32_t *)malloc((size_t)g.n * sizeof(uint32_t));
+    int ok = gi && ls && lt && ln && inner && own && nbr && en && sums && ys && yt && yn;
+    int64_t launches = 0, rounds_total = 0, events = 0;
+    uint64_t flips = 0;
+    while (ok) {
+        int any_live = 0;
+        for (int64_t c = 0; c < g.n && !any_live; ++c) any_live = t[c] < T;
+        if (!any_live || launches >= max_launches) break;
+        ++launches;
+        memcpy(ys, s, (size_t)g.n);
+        memcpy(yt, t, (size_t)g.n * sizeof(double));
+        memcpy(yn, n, (size_t)g.n * sizeof(uint32_t));
+        for (int64_t ti = 0; ti < ntiles; ++ti) {
+            int64_t tc[3] = {ti % cnt[0], (ti / cnt[0]) % cnt[1], ti / (cnt[0] * cnt[1])};
+            int64_t rb[3], org[3], olo[3], ohi[3], ring[3];
+            for (int d = 0; d < 3; ++d) {
+                int64_t lo = tc[d] * w[d];
+                int64_t ww = g.L[d] - lo < w[d] ? g.L[d] - lo : w[d];
+                ring[d] = span[d] ? 0 : 1;
+                int64_t rin = span[d] ? g.L[d] : ww + 2 * gw[d];
+                rb[d] = rin + 2 * ring[d];
+                org[d] = span[d] ? 0 : lo - gw[d] - 1;       /* ring origin */
+                olo[d] = span[d] ? 0 : gw[d] + 1;
+                ohi[d] = span[d] ? g.L[d] : gw[d] + 1 + ww;
+            }
+            int64_t m = rb[0] * rb[1] * rb[2];
+            for (int64_t j = 0; j < m; ++j) {
+                int64_t q[3] = {j % rb[0], (j / rb[0]) % rb[1], j / (rb[0] * rb[1])};
+                int64_t gc[3];
+                int in = 1, ow = 1;
+                for (int d = 0; d < 3; ++d) {
+                    gc[d] = ((org[d] + q[d]) % g.L[d] + g.L[d]) % g.L[d];
+                    if (!span[d] && (q[d] == 0 || q[d] == rb[d] - 1)) in = 0;
+                    if (q[d] < olo[d] || q[d] >= ohi[d]) ow = 0;
+                }
+                int64_t c = gc[0] + g.L[0] * (gc[1] + g.L[1] * gc[2]);
+                gi[j] = c; ls[j] = s[c]; lt[j] = t[c]; ln[j] = n[c];
+                inner[j] = (uint8_t)in; own[j] = (uint8_t)ow;
+                for (int k = 0; k < g.z; ++k) {
+                    int d = k / 2;
+                    int64_t qq[3] = {q[0], q[1], q[2]};
+                    if (k & 1) qq[d] = span[d] ? (qq[d] + rb[d] - 1) % rb[d] : qq[d] - 1;
+                    else       qq[d] = span[d] ? (qq[d] + 1) % rb[d] : qq[d] + 1;
+                    nbr[j * 6 + k] = qq[0] + rb[0] * (qq[1] + rb[1] * qq[2]);
+                }
+            }
+            for (int64_t r = 0; r < max_rounds; ++r) {
+                int64_t q = 0;
+                for (int64_t j = 0; j < m; ++j) {
+                    if (!inner[j] || !(lt[j] < T)) continue;
+                    int okc = 1, sum = 0;
+                    for (int k = 0; k < g.z; ++k) {
+                        int64_t b = nbr[j * 6 + k];
+                        if (!precedes(lt[j], gi[j], lt[b], gi[b])) { okc = 0; break; }
+                        sum += ls[b];
+                    }
+                    if (okc) { en[q] = j; sums[q] = sum; ++q; }
+                }
+                if (q == 0) break;
+                ++rounds_total;
+                for (int64_t i = 0; i < q; ++i) {
+                    int64_t j = en[i];
+                    uint32_t ctr[4] = {ln[j], (uint32_t)gi[j], 0u, 0u}, y[4];
+                    oracle_philox(ctr, seed, y, 1);
+                    int idx = (sums[i] + g.z) / 2 + (g.z + 1) * (ls[j] + 1) / 2;
+                    if ((uint64_t)y[2] < thr[idx]) ls[j] = (int8_t)(-ls[j]);
+                    uint64_t wv = ((uint64_t)y[1] << 32) | y[0];
+                    double e;
+                    oracle_neg_log_words(&wv, &e, 1);
+                    lt[j] = lt[j] + e / rate;
+                    ln[j] = ln[j] + 1u;
+                }
+            }
+            for (int64_t j = 0; j < m; ++j) {
+                if (!inner[j] || (!merge_ghosts && !own[j])) continue;
+                int64_t c = gi[j];
+                if (ln[j] > yn[c] || (own[j] && !merge_ghosts)) {
+                    ys[c] = ls[j]; yt[c] = lt[j]; yn[c] = ln[j];
+                }
+            }
+        }
+        for (int64_t c = 0; c < g.n; ++c) {
+            events += (int64_t)(yn[c] - n[c]);
+            if (ys[c] != s[c]) flips += 0;   /* flips are not tracked here */
+        }
+        memcpy(s, ys, (size_t)g.n);
+        memcpy(t, yt, (size_t)g.n * sizeof(double));
+        memcpy(n, yn, (size_t)g.n * sizeof(uint32_t));
+    }
+    free(gi); free(ls); free(lt); free(ln); free(inner); free(own); free(nbr);
+    free(en); free(sums); free(ys); free(yt); free(yn);
+    if (!ok) return -1;
+    if (stats) { stats[0] = launches; stats[1] = rounds_total; }
+    if (flips_out) *flips_out = flips;
+    return events;
+}

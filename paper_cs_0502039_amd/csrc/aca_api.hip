@@ -1,11 +1,12 @@
 // aca_api.hip -- C-ABI of libaca (declared in include/aca.h).
 //
 // Host side of the conservative simulation: argument checks, the flip
-// thresholds, the tile plan, and the launch loop of aca_advance.  The loop
-// advances every tile region once per launch from a snapshot of the whole
-// lattice (double buffer: the caller's state and a copy in scratch), reads
-// back the per-launch counters, and stops when no owned cell has an arrival
-// before the horizon.  A launch that applies nothing while arrivals are due
+// thresholds, the tile plan, and the launch loop of aca_advance.  The caller's
+// state is packed into working words (two snapshots in scratch); each launch
+// advances every tile region from one snapshot and merges all copies into the
+// other; the loop reads back per-launch counters and stops when no owned cell
+// has an arrival before the horizon; the final snapshot is unpacked into the
+// caller's buffers.  A launch that applies nothing while arrivals are due
 // is reported as ACA_ENOPROGRESS: the cell holding the globally earliest
 // arrival always sees current neighbours at load time and must be able to
 // move (the deadlock-freedom argument of Fig. 3.1 and Fig. 3.4).
@@ -58,20 +59,28 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
+// Scratch: two snapshots of working words (key, time) and the counters.
 struct ScratchLayout {
-    size_t s_off, t_off, n_off, ctr_off, total;
+    size_t key_off[2], time_off[2], ctr_off, total;
 };
 
 ScratchLayout scratch_layout(uint64_t n)
 {
     ScratchLayout l;
-    l.s_off = 0;
-    l.t_off = align_up(l.s_off + n);
-    l.n_off = align_up(l.t_off + 8 * n);
-    l.ctr_off = align_up(l.n_off + 4 * n);
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b) {
+        l.key_off[b] = off;
+        off = align_up(off + 8 * n);
+        l.time_off[b] = off;
+        off = align_up(off + 8 * n);
+    }
+    l.ctr_off = off;
     l.total = l.ctr_off + kAlign;
     return l;
 }
+
+// Counter words in scratch: the visit counters, then the pack/unpack sums.
+enum : int { kSumStart = 8, kSumEnd = 9, kSumFlips = 10, kCounterWords = 12 };
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -131,11 +140,12 @@ int build_thresholds(const aca_params *p, uint64_t *thr)
 struct aca_lattice {
     aca_params p;
     uint64_t n;
-    int8_t *s[2];
-    double *t[2];
-    uint32_t *cnt[2];
+    int8_t *s;                      // caller's state buffers
+    double *t;
+    uint32_t *cnt;
+    unsigned long long *key[2];     // working snapshots in scratch
+    unsigned long long *time[2];
     unsigned long long *counters;   // device, in scratch
-    int cur;                        // which copy holds the current state
     bool initialized;
     double last_T;
     aca_tuning tun;                 // as requested (0 / -1 = automatic)
@@ -170,7 +180,7 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
     }
 }
 
-aca_status make_plan(const aca_lattice *lat, double T, int in, Plan *plan)
+aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
 {
     const aca_params &p = lat->p;
     aca_tuning t;
@@ -185,6 +195,9 @@ aca_status make_plan(const aca_lattice *lat, double T, int in, Plan *plan)
     if (lat->tun.block > 0) t.block = lat->tun.block;
     if (t.block % 64 != 0 || t.block < 64 || t.block > 1024)
         return fail(ACA_EINVAL, "block %d must be a multiple of 64 in [64, 1024]", t.block);
+    // a cell applies at most one arrival per sweep; per-visit flip counts are
+    // kept in 16 bits
+    t.max_sweeps = std::min(t.max_sweeps, 65535);
 
     aca::VisitArgs &a = plan->a;
     memset(&a, 0, sizeof a);
@@ -213,9 +226,6 @@ aca_status make_plan(const aca_lattice *lat, double T, int in, Plan *plan)
     uint64_t hb;
     memcpy(&hb, &T, sizeof hb);
     a.horizon_bits = hb;
-    const int out = 1 - in;
-    a.s_in = lat->s[in]; a.t_in = lat->t[in]; a.n_in = lat->cnt[in];
-    a.s_out = lat->s[out]; a.t_out = lat->t[out]; a.n_out = lat->cnt[out];
     a.counters = lat->counters;
     memcpy(a.thr, lat->thr, sizeof a.thr);
     plan->block = t.block;
@@ -231,9 +241,9 @@ aca_status make_plan(const aca_lattice *lat, double T, int in, Plan *plan)
     return ACA_OK;
 }
 
-// Bytes one launch must move: for each tile, (spin, time) of its whole region
-// box and the counts of its simulated cells in, (spin, time, count) of its own
-// cells out.
+// Bytes one launch must move: for each tile, the two working words of its
+// whole region box in and those of its own cells out (16 B per cell each way;
+// merges of ghost copies come on top and are not counted).
 uint64_t launch_region_bytes(int dim, const aca::VisitArgs &a)
 {
     uint64_t total = 0;
@@ -257,7 +267,8 @@ uint64_t launch_region_bytes(int dim, const aca::VisitArgs &a)
                     box *= (uint64_t)(rin + (a.span[d] ? 0 : 2));
                     (void)dim;
                 }
-                if (any) total += count * (9 * box + 4 * inner + 13 * own);
+                if (any) total += count * (16 * box + 16 * own);
+                (void)inner;
             }
     return total;
 }
@@ -319,14 +330,14 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
     lat->p = *p;
     lat->n = n;
     char *sc = static_cast<char *>(d_scratch);
-    lat->s[0] = d_spin;
-    lat->t[0] = d_time;
-    lat->cnt[0] = d_count;
-    lat->s[1] = reinterpret_cast<int8_t *>(sc + sl.s_off);
-    lat->t[1] = reinterpret_cast<double *>(sc + sl.t_off);
-    lat->cnt[1] = reinterpret_cast<uint32_t *>(sc + sl.n_off);
+    lat->s = d_spin;
+    lat->t = d_time;
+    lat->cnt = d_count;
+    for (int b = 0; b < 2; ++b) {
+        lat->key[b] = reinterpret_cast<unsigned long long *>(sc + sl.key_off[b]);
+        lat->time[b] = reinterpret_cast<unsigned long long *>(sc + sl.time_off[b]);
+    }
     lat->counters = reinterpret_cast<unsigned long long *>(sc + sl.ctr_off);
-    lat->cur = 0;
     lat->initialized = false;
     lat->last_T = 0.0;
     memset(&lat->tun, 0, sizeof lat->tun);
@@ -370,7 +381,7 @@ ACA_EXPORT aca_status aca_get_tuning(const aca_lattice *lat, aca_tuning *out)
 {
     if (!lat || !out) return fail(ACA_EINVAL, "NULL argument");
     Plan plan;
-    aca_status st = make_plan(lat, 1.0, 0, &plan);
+    aca_status st = make_plan(lat, 1.0, &plan);
     if (st != ACA_OK) return st;
     memset(out, 0, sizeof *out);
     out->struct_size = sizeof *out;
@@ -389,8 +400,7 @@ ACA_EXPORT aca_status aca_init(aca_lattice *lat, void *stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(aca::launch_init(lat->p.dim, lat->p.L, lat->n, (uint32_t)lat->p.seed,
                              (uint32_t)(lat->p.seed >> 32), lat->p.rate, lat->p.init,
-                             lat->s[0], lat->t[0], lat->cnt[0], s));
-    lat->cur = 0;
+                             lat->s, lat->t, lat->cnt, s));
     lat->initialized = true;
     lat->last_T = 0.0;
     memset(&lat->stats, 0, sizeof lat->stats);
@@ -403,7 +413,6 @@ ACA_EXPORT aca_status aca_resume(aca_lattice *lat, double T_done)
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
     if (!is_finite(T_done) || T_done < 0.0)
         return fail(ACA_EINVAL, "T_done must be finite and >= 0");
-    lat->cur = 0;
     lat->initialized = true;
     lat->last_T = T_done;
     memset(&lat->stats, 0, sizeof lat->stats);
@@ -427,39 +436,47 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     const auto t0 = std::chrono::steady_clock::now();
     Plan plan;
-    aca_status st = make_plan(lat, T, lat->cur, &plan);
+    aca_status st = make_plan(lat, T, &plan);
     if (st != ACA_OK) return st;
     if (plan.lds > 64 * 1024) HIP_TRY(aca::set_visit_lds_limit(plan.lds));
-    unsigned long long host_ctr[aca::kNumCounters];
+    unsigned long long host_ctr[kCounterWords];
     const uint64_t tiles = (uint64_t)plan.a.ntiles[0] * plan.a.ntiles[1] * plan.a.ntiles[2];
     const uint64_t bytes_per_launch = launch_region_bytes(lat->p.dim, plan.a);
-    // Safety net: every launch applies at least one arrival, so the loop ends;
-    // this bound only turns a pathological schedule into an error.
+
+    // caller state -> snapshot 0; snapshot 1 starts below every copy (zero)
+    HIP_TRY(hipMemsetAsync(lat->counters, 0, sizeof host_ctr, s));
+    HIP_TRY(aca::launch_pack(lat->n, lat->s, lat->t, lat->cnt, lat->key[0], lat->time[0],
+                             lat->counters + kSumStart, s));
+    HIP_TRY(hipMemsetAsync(lat->key[1], 0, 8 * lat->n, s));
+    HIP_TRY(hipMemsetAsync(lat->time[1], 0, 8 * lat->n, s));
+    int cur = 0;
+    // Every launch applies at least the globally earliest due arrival, so the
+    // loop ends; the bound only turns a pathological schedule into an error.
     const uint64_t max_launches = 100000;
     for (uint64_t launch = 0;; ++launch) {
         if (launch >= max_launches)
             return fail(ACA_ENOPROGRESS, "horizon not reached after %llu launches",
                         (unsigned long long)launch);
-        const int in = lat->cur, out = 1 - in;
-        plan.a.s_in = lat->s[in]; plan.a.t_in = lat->t[in]; plan.a.n_in = lat->cnt[in];
-        plan.a.s_out = lat->s[out]; plan.a.t_out = lat->t[out]; plan.a.n_out = lat->cnt[out];
-        HIP_TRY(hipMemsetAsync(lat->counters, 0, sizeof host_ctr, s));
+        const int out = 1 - cur;
+        plan.a.key_in = lat->key[cur];
+        plan.a.time_in = lat->time[cur];
+        plan.a.key_out = lat->key[out];
+        plan.a.time_out = lat->time[out];
+        HIP_TRY(hipMemsetAsync(lat->counters, 0, 8 * aca::kNumCounters, s));
         HIP_TRY(hipEventRecord(lat->ev_start, s));
         HIP_TRY(aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
         HIP_TRY(hipEventRecord(lat->ev_stop, s));
-        HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, sizeof host_ctr,
+        HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, 8 * aca::kNumCounters,
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         float kms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&kms, lat->ev_start, lat->ev_stop));
-        lat->cur = out;
+        cur = out;
         aca_stats &S = lat->stats;
         S.kernel_ms += kms;
         S.region_bytes += bytes_per_launch;
         S.launches += 1;
         S.visits += tiles;
-        S.events += host_ctr[aca::kEvents];
-        S.flips += host_ctr[aca::kFlips];
         S.ghost_events += host_ctr[aca::kGhostEvents];
         S.sweeps += host_ctr[aca::kSweeps];
         S.cell_checks += host_ctr[aca::kChecks];
@@ -469,14 +486,13 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
                         "still had arrivals before the horizon",
                         (unsigned long long)host_ctr[aca::kLiveTiles]);
     }
-    if (lat->cur != 0) {
-        HIP_TRY(hipMemcpyAsync(lat->s[0], lat->s[1], lat->n, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(lat->t[0], lat->t[1], 8 * lat->n, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(lat->cnt[0], lat->cnt[1], 4 * lat->n,
-                               hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        lat->cur = 0;
-    }
+    HIP_TRY(aca::launch_unpack(lat->n, lat->key[cur], lat->time[cur], lat->s, lat->t,
+                               lat->cnt, lat->counters + kSumEnd, s));
+    HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, sizeof host_ctr, hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    lat->stats.events += host_ctr[kSumEnd] - host_ctr[kSumStart];
+    lat->stats.flips += host_ctr[kSumFlips];
     lat->last_T = T;
     lat->stats.last_T = T;
     lat->stats.device_ms +=
@@ -497,12 +513,11 @@ ACA_EXPORT aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int c = lat->cur;
-    if (h_spin) HIP_TRY(hipMemcpyAsync(h_spin, lat->s[c], lat->n, hipMemcpyDeviceToHost, s));
+    if (h_spin) HIP_TRY(hipMemcpyAsync(h_spin, lat->s, lat->n, hipMemcpyDeviceToHost, s));
     if (h_time)
-        HIP_TRY(hipMemcpyAsync(h_time, lat->t[c], 8 * lat->n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_time, lat->t, 8 * lat->n, hipMemcpyDeviceToHost, s));
     if (h_count)
-        HIP_TRY(hipMemcpyAsync(h_count, lat->cnt[c], 4 * lat->n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h_count, lat->cnt, 4 * lat->n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return ACA_OK;
 }

@@ -17,6 +17,13 @@ enum Counter : int {
     kNumCounters = 8
 };
 
+// Working state of a cell during aca_advance, two 64-bit words:
+//   key  = n << 32 | f << 1 | (spin < 0)   n arrivals applied since time 0,
+//                                          f spin flips since the advance began
+//   time = bit pattern of the pending arrival time (> 0, so ordered as uint64)
+// Both words only grow as the cell's trajectory advances, so the most
+// advanced of several copies of a cell is their element-wise maximum.
+//
 // Everything a tile visit needs.  One workgroup simulates one tile region:
 // the tile's own cells, `ghost` extra cells on each side of every direction
 // the tile does not span, and a frozen one-cell ring around that.  Along a
@@ -33,12 +40,10 @@ struct VisitArgs {
     int32_t unit_rate;
     double rate;
     uint64_t horizon_bits;     // bit pattern of the horizon T > 0
-    const int8_t *s_in;
-    const double *t_in;
-    const uint32_t *n_in;
-    int8_t *s_out;
-    double *t_out;
-    uint32_t *n_out;
+    const unsigned long long *key_in;     // snapshot read by every region
+    const unsigned long long *time_in;
+    unsigned long long *key_out;          // merged record (element-wise max)
+    unsigned long long *time_out;
     unsigned long long *counters;
     uint64_t thr[14];
 };
@@ -52,6 +57,18 @@ hipError_t launch_init(int dim, const int32_t *L, uint64_t n_cells, uint32_t key
 
 hipError_t launch_visit(int dim, const VisitArgs &a, int block, size_t lds,
                         hipStream_t stream);
+
+// Caller state (s, t, n) -> working words (flip count 0); adds sum of n to
+// *sum_n.
+hipError_t launch_pack(uint64_t n_cells, const int8_t *s, const double *t,
+                       const uint32_t *n, unsigned long long *key,
+                       unsigned long long *time, unsigned long long *sum_n,
+                       hipStream_t stream);
+
+// Working words -> caller state; adds sum of n and sum of f to sums[0..1].
+hipError_t launch_unpack(uint64_t n_cells, const unsigned long long *key,
+                         const unsigned long long *time, int8_t *s, double *t,
+                         uint32_t *n, unsigned long long *sums, hipStream_t stream);
 
 hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out,
                          uint64_t count, hipStream_t stream);

@@ -5,7 +5,9 @@
 // visit_kernel      one workgroup per tile region (the aggregation of
 //                   Fig. 3.3/3.4): the region is loaded into LDS, its cells
 //                   run the asynchronous conservative rule of Fig. 3.1 until
-//                   none can move, and the tile's own cells are written back.
+//                   none can move, and every simulated copy is merged into
+//                   the next snapshot.
+// pack / unpack     caller's (spin, time, count) arrays <-> working words.
 //
 // Region layout.  A tile owns an axis-aligned box of cells.  Along every
 // direction it does not span, the region adds `ghost` cells on both sides
@@ -72,14 +74,9 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint64_t pack_cell(double t, int8_t s)
-{
-    return (uint64_t)__double_as_longlong(t) | (s < 0 ? kSignBit : 0ull);
-}
-
 // LDS carve-up shared with visit_lds_bytes().
 struct LdsPlan {
-    size_t thr_off, ctr_off, ts_off, n_off, list_off, total;
+    size_t thr_off, ctr_off, ts_off, n_off, f_off, list_off, total;
 };
 
 __host__ __device__ inline LdsPlan lds_plan(int box_max, int nwaves)
@@ -89,7 +86,8 @@ __host__ __device__ inline LdsPlan lds_plan(int box_max, int nwaves)
     p.ctr_off = 128;                                 // int counters[8]
     p.ts_off = 160;                                  // uint64 ts[box_max]
     p.n_off = p.ts_off + 8 * (size_t)box_max;        // uint32 n[box_max]
-    p.list_off = p.n_off + 4 * (size_t)box_max;      // uint32 per wave 2*kListCap
+    p.f_off = p.n_off + 4 * (size_t)box_max;         // uint16 flips[box_max]
+    p.list_off = p.f_off + 2 * (size_t)box_max;      // uint32 per wave 2*kListCap
     p.list_off = (p.list_off + 15) & ~(size_t)15;
     p.total = p.list_off + (size_t)nwaves * 2 * kListCap * 4;
     return p;
@@ -173,6 +171,7 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     int *ctr = reinterpret_cast<int *>(lds + plan.ctr_off);
     uint64_t *ts = reinterpret_cast<uint64_t *>(lds + plan.ts_off);
     uint32_t *nl = reinterpret_cast<uint32_t *>(lds + plan.n_off);
+    uint16_t *fl = reinterpret_cast<uint16_t *>(lds + plan.f_off);
     uint32_t *meta_list = reinterpret_cast<uint32_t *>(lds + plan.list_off) +
                           wave * 2 * kListCap;
     uint32_t *gidx_list = meta_list + kListCap;
@@ -196,8 +195,12 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         }
         const uint32_t gi = (uint32_t)g[0] + (uint32_t)gs1 * (uint32_t)g[1] +
                             (uint32_t)gs2 * (uint32_t)g[2];
-        ts[j] = pack_cell(a.t_in[gi], a.s_in[gi]);
-        if (in_core) nl[j] = a.n_in[gi];
+        const unsigned long long key = a.key_in[gi];
+        ts[j] = (uint64_t)a.time_in[gi] | ((key & 1ull) << 63);
+        if (in_core) {
+            nl[j] = (uint32_t)(key >> 32);
+            fl[j] = 0;
+        }
     }
     __syncthreads();
 
@@ -252,6 +255,7 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
                 const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
                 const uint64_t sign = (wd & kSignBit) ^ (flip ? kSignBit : 0ull);
                 nl[bi] = k + 1u;
+                fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 lds_store_word(&ts[bi], (uint64_t)__double_as_longlong(tnext) | sign);
                 if (own_cell) {
@@ -349,33 +353,38 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     }
     __syncthreads();
 
-    // ---- write back the tile's own cells; detect remaining work
+    // ---- merge every owned copy and every ghost copy that moved into the
+    // ---- next snapshot; detect owned cells with arrivals still due
     bool live = false;
-    {
-        const int ow0 = ohi[0] - olo[0], ow1 = ohi[1] - olo[1];
-        const int own_count = ow0 * ow1 * (ohi[2] - olo[2]);
-        for (int j = tid; j < own_count; j += nthreads) {
-            int o[3];
-            o[0] = j % ow0;
-            const int r = j / ow0;
-            o[1] = r % ow1;
-            o[2] = r / ow1;
-            int g[3], q[3];
+    for (int j = tid; j < inner; j += nthreads) {
+        int p[3];
+        p[0] = j % rin[0];
+        const int r = j / rin[0];
+        p[1] = r % rin[1];
+        p[2] = r / rin[1];
+        int g[3];
+        bool own_cell = true;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int pd = olo[d] + o[d];
-                q[d] = pd + ring[d];
-                g[d] = (d < DIM) ? wrap_side(org[d] + pd, side[d]) : 0;
-            }
-            const int bi = q[0] + sbox[1] * q[1] + sbox[2] * q[2];
-            const uint32_t gi = (uint32_t)g[0] + (uint32_t)gs1 * (uint32_t)g[1] +
-                                (uint32_t)gs2 * (uint32_t)g[2];
-            const uint64_t wd = ts[bi];
-            a.t_out[gi] = __longlong_as_double((long long)(wd & kTimeMask));
-            a.s_out[gi] = (wd >> 63) ? (int8_t)-1 : (int8_t)1;
-            a.n_out[gi] = nl[bi];
-            live = live || (wd & kTimeMask) < horizon;
+        for (int d = 0; d < 3; ++d) {
+            g[d] = (d < DIM) ? wrap_side(org[d] + p[d], side[d]) : 0;
+            own_cell = own_cell && p[d] >= olo[d] && p[d] < ohi[d];
         }
+        const int bi = (p[0] + ring[0]) + sbox[1] * (p[1] + ring[1]) +
+                       sbox[2] * (p[2] + ring[2]);
+        const uint32_t gi = (uint32_t)g[0] + (uint32_t)gs1 * (uint32_t)g[1] +
+                            (uint32_t)gs2 * (uint32_t)g[2];
+        const uint32_t n_copy = nl[bi];
+        const unsigned long long key_in = a.key_in[gi];
+        const uint32_t n_in = (uint32_t)(key_in >> 32);
+        const uint64_t wd = ts[bi];
+        if (own_cell || n_copy != n_in) {
+            const unsigned long long f = ((key_in >> 1) & 0x7FFFFFFFull) + fl[bi];
+            const unsigned long long key = ((unsigned long long)n_copy << 32) | (f << 1) |
+                                           (wd >> 63);
+            atomicMax(&a.key_out[gi], key);
+            atomicMax(&a.time_out[gi], (unsigned long long)(wd & kTimeMask));
+        }
+        if (own_cell) live = live || (wd & kTimeMask) < horizon;
     }
     // ---- counters
     atomicAdd(&ctr[3], (int)my_events);
@@ -392,6 +401,49 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         atomicAdd(&gc[kSweeps], (unsigned long long)sweeps);
         if (any_live) atomicAdd(&gc[kLiveTiles], 1ull);
     }
+}
+
+// ----------------------------------------------------------------- pack
+
+__device__ __forceinline__ void block_add(unsigned long long *dst, unsigned long long v)
+{
+    // wavefront reduction, then one atomic per wavefront
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+}
+
+__global__ void pack_kernel(uint64_t n_cells, const int8_t *s, const double *t,
+                            const uint32_t *n, unsigned long long *key,
+                            unsigned long long *time, unsigned long long *sum_n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long acc = 0;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+         c += stride) {
+        key[c] = ((unsigned long long)n[c] << 32) | (s[c] < 0 ? 1ull : 0ull);
+        time[c] = (unsigned long long)__double_as_longlong(t[c]);
+        acc += n[c];
+    }
+    block_add(sum_n, acc);
+}
+
+__global__ void unpack_kernel(uint64_t n_cells, const unsigned long long *key,
+                              const unsigned long long *time, int8_t *s, double *t,
+                              uint32_t *n, unsigned long long *sums)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long acc_n = 0, acc_f = 0;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+         c += stride) {
+        const unsigned long long k = key[c];
+        s[c] = (k & 1ull) ? (int8_t)-1 : (int8_t)1;
+        n[c] = (uint32_t)(k >> 32);
+        t[c] = __longlong_as_double((long long)time[c]);
+        acc_n += k >> 32;
+        acc_f += (k >> 1) & 0x7FFFFFFFull;
+    }
+    block_add(&sums[0], acc_n);
+    block_add(&sums[1], acc_f);
 }
 
 // ----------------------------------------------------------------- checks
@@ -462,6 +514,27 @@ hipError_t launch_visit(int dim, const VisitArgs &a, int block, size_t lds,
         hipLaunchKernelGGL(visit_kernel<3>, dim3(tiles), dim3(block), lds, stream, a);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(uint64_t n_cells, const int8_t *s, const double *t,
+                       const uint32_t *n, unsigned long long *key,
+                       unsigned long long *time, unsigned long long *sum_n,
+                       hipStream_t stream)
+{
+    const unsigned block = 256;
+    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_cells, block)), dim3(block), 0, stream,
+                       n_cells, s, t, n, key, time, sum_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(uint64_t n_cells, const unsigned long long *key,
+                         const unsigned long long *time, int8_t *s, double *t,
+                         uint32_t *n, unsigned long long *sums, hipStream_t stream)
+{
+    const unsigned block = 256;
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_cells, block)), dim3(block), 0,
+                       stream, n_cells, key, time, s, t, n, sums);
     return hipGetLastError();
 }
 

@@ -468,3 +468,30 @@ def test_time_only_efficiency_matches_section4(dim, L, T, paper):
     steady = rec[rounds // 4: rounds * 3 // 4] / N
     assert abs(steady.mean() - paper) < 0.004, steady.mean()
     assert abs(ev / N - T) < 0.05 * T   # about one arrival per unit time per cell
+
+
+@pytest.mark.parametrize("params,T", SCHED_CASES)
+@pytest.mark.parametrize("tile,ghost,rounds", [((64, 64, 16), (4, 4, 2), 32),
+                                               ((16, 8, 8), (3, 2, 1), 5),
+                                               ((7, 5, 3), (2, 2, 1), 1 << 30),
+                                               ((9, 9, 9), (0, 0, 0), 1)])
+def test_ghost_merge_schedule_identical(params, T, tile, ghost, rounds):
+    """The GPU library's launch schedule (all tiles against one snapshot, ghost
+    zones, copies merged by most arrivals applied) reaches the heap's state."""
+    s, t, n, ev, fl = oracle.simulate(params, T)
+    s2, t2, n2 = oracle.init(params)
+    ev2, launches, nr = oracle.run_ghost_merge(params, T, s2, t2, n2, tile, ghost, rounds)
+    assert ev2 == ev
+    assert np.array_equal(s, s2) and np.array_equal(t, t2) and np.array_equal(n, n2)
+
+
+def test_ghost_copies_must_be_merged():
+    """Writing back only owned copies loses consistency (a ghost copy can run ahead
+    of its owner and an owned neighbour may rely on it): spins then differ."""
+    params = P(2, (200, 131), 0.4406868, seed=11)
+    s, t, n, ev, fl = oracle.simulate(params, 20.0)
+    s2, t2, n2 = oracle.init(params)
+    oracle.run_ghost_merge(params, 20.0, s2, t2, n2, (64, 64), (4, 4), 32,
+                           merge_ghosts=False)
+    assert np.array_equal(t, t2) and np.array_equal(n, n2)   # clocks never depend on spins
+    assert not np.array_equal(s, s2)
