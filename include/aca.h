@@ -74,7 +74,7 @@ typedef struct aca_params {
  * for Fig. 3.4), only speed.  struct_size must be sizeof(aca_tuning).
  *  tile[d]    own cells of a workgroup tile along d (0 = automatic)
  *  ghost[d]   extra cells simulated on each side and discarded (-1 = auto)
- *  max_sweeps sweeps of a tile per visit (0 = automatic)
+ *  max_sweeps worklist rounds of a tile per visit (0 = automatic)
  *  block      threads per workgroup, multiple of 64 up to 1024 (0 = auto) */
 typedef struct aca_tuning {
     uint32_t struct_size;
@@ -90,12 +90,12 @@ typedef struct aca_stats {
     uint32_t pad_;
     uint64_t launches;      /* visit-kernel launches */
     uint64_t visits;        /* workgroup tile visits */
-    uint64_t sweeps;        /* tile sweeps summed over visits */
+    uint64_t sweeps;        /* worklist rounds summed over tile visits */
     uint64_t events;        /* arrivals applied (spin-updates), exact */
     uint64_t flips;         /* of which reversed the spin, exact */
     uint64_t ghost_events;  /* arrivals applied to ghost copies in their
                                region (redundant work; some are merged) */
-    uint64_t cell_checks;   /* enabling tests evaluated */
+    uint64_t cell_checks;   /* enabling tests evaluated (scan + re-tests) */
     double last_T;          /* horizon reached so far */
     double device_ms;       /* time spent inside aca_advance (wall, ms) */
     double kernel_ms;       /* visit-kernel time, HIP events on the stream (ms) */

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libaca.so")
-SOURCES = ("aca_api.hip", "aca_kernels.hip")
+SOURCES = ("aca_api.hip", "aca_kernels.hip", "aca_visit_fast.hip")
 ARCH = os.environ.get("ACA_OFFLOAD_ARCH", "gfx950")
 
 

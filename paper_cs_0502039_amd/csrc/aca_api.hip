@@ -28,10 +28,6 @@
 
 #define ACA_EXPORT extern "C" __attribute__((visibility("default")))
 
-namespace aca {
-hipError_t set_visit_lds_limit(size_t bytes);
-}
-
 namespace {
 
 thread_local std::string g_error;
@@ -161,6 +157,7 @@ struct Plan {
     aca::VisitArgs a;
     int block;
     size_t lds;
+    bool fast;      // no direction spanned: the pitched-box kernel
 };
 
 // Automatic schedule knobs; every choice gives the same result.
@@ -168,15 +165,15 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
 {
     if (p.dim == 1) {
         t->tile[0] = 8192; t->ghost[0] = 64;
-        t->max_sweeps = 64; t->block = 256;
+        t->max_sweeps = 512; t->block = 256;
     } else if (p.dim == 2) {
-        t->tile[0] = 64; t->tile[1] = 64;
+        t->tile[0] = 64; t->tile[1] = 56;
         t->ghost[0] = 4; t->ghost[1] = 4;
         t->max_sweeps = 32; t->block = 512;
     } else {
         t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 8;
         t->ghost[0] = 2; t->ghost[1] = 2; t->ghost[2] = 2;
-        t->max_sweeps = 24; t->block = 512;
+        t->max_sweeps = 256; t->block = 512;
     }
 }
 
@@ -229,10 +226,21 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
     a.counters = lat->counters;
     memcpy(a.thr, lat->thr, sizeof a.thr);
     plan->block = t.block;
-    plan->lds = aca::visit_lds_bytes(p.dim, a, t.block);
     int dev_lds = 0;
     HIP_TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                   lat->device));
+    bool spans = false;
+    for (int d = 0; d < p.dim; ++d) spans = spans || a.span[d];
+    plan->fast = !spans && aca::visit_fast_box(p.dim, a) <= 65535 &&
+                 aca::visit_fast_lds_bytes(p.dim, a) <= (size_t)dev_lds;
+    if (plan->fast) {
+        plan->lds = aca::visit_fast_lds_bytes(p.dim, a);
+        return ACA_OK;
+    }
+    if (aca::visit_inner_max(p.dim, a) > 65535)
+        return fail(ACA_EINVAL, "a tile region of %d cells exceeds 65535 simulated cells",
+                    aca::visit_inner_max(p.dim, a));
+    plan->lds = aca::visit_lds_bytes(p.dim, a, t.block);
     if (plan->lds > (size_t)dev_lds)
         return fail(ACA_EINVAL, "tile region needs %zu B of LDS, device has %d B",
                     plan->lds, dev_lds);
@@ -438,7 +446,9 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
     Plan plan;
     aca_status st = make_plan(lat, T, &plan);
     if (st != ACA_OK) return st;
-    if (plan.lds > 64 * 1024) HIP_TRY(aca::set_visit_lds_limit(plan.lds));
+    if (plan.lds > 64 * 1024)
+        HIP_TRY(plan.fast ? aca::set_visit_fast_lds_limit(plan.lds)
+                          : aca::set_visit_lds_limit(plan.lds));
     unsigned long long host_ctr[kCounterWords];
     const uint64_t tiles = (uint64_t)plan.a.ntiles[0] * plan.a.ntiles[1] * plan.a.ntiles[2];
     const uint64_t bytes_per_launch = launch_region_bytes(lat->p.dim, plan.a);
@@ -464,7 +474,8 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
         plan.a.time_out = lat->time[out];
         HIP_TRY(hipMemsetAsync(lat->counters, 0, 8 * aca::kNumCounters, s));
         HIP_TRY(hipEventRecord(lat->ev_start, s));
-        HIP_TRY(aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
+        HIP_TRY(plan.fast ? aca::launch_visit_fast(lat->p.dim, plan.a, plan.block, plan.lds, s)
+                          : aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
         HIP_TRY(hipEventRecord(lat->ev_stop, s));
         HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, 8 * aca::kNumCounters,
                                hipMemcpyDeviceToHost, s));

@@ -12,7 +12,7 @@ enum Counter : int {
     kFlips = 1,         // of which reversed the spin
     kGhostEvents = 2,   // arrivals applied to ghost copies (discarded)
     kLiveTiles = 3,     // tiles with an owned cell still before the horizon
-    kSweeps = 4,        // sweeps summed over tile visits
+    kSweeps = 4,        // worklist rounds summed over tile visits
     kChecks = 5,        // enabling tests evaluated
     kNumCounters = 8
 };
@@ -48,8 +48,10 @@ struct VisitArgs {
     uint64_t thr[14];
 };
 
-// Bytes of dynamic LDS a visit needs for the largest region of this plan.
+// Bytes of dynamic LDS a visit needs for the largest region of this plan, and
+// the number of simulated cells of that region (must stay below 65536).
 size_t visit_lds_bytes(int dim, const VisitArgs &a, int block);
+int visit_inner_max(int dim, const VisitArgs &a);
 
 hipError_t launch_init(int dim, const int32_t *L, uint64_t n_cells, uint32_t key_lo,
                        uint32_t key_hi, double rate, int init, int8_t *s, double *t,
@@ -57,6 +59,15 @@ hipError_t launch_init(int dim, const int32_t *L, uint64_t n_cells, uint32_t key
 
 hipError_t launch_visit(int dim, const VisitArgs &a, int block, size_t lds,
                         hipStream_t stream);
+hipError_t set_visit_lds_limit(size_t bytes);
+
+// The variant for tiles that span no direction (aca_visit_fast.hip): its LDS
+// need, its region box size (must stay below 65536), launch and LDS limit.
+size_t visit_fast_lds_bytes(int dim, const VisitArgs &a);
+int visit_fast_box(int dim, const VisitArgs &a);
+hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
+                             hipStream_t stream);
+hipError_t set_visit_fast_lds_limit(size_t bytes);
 
 // Caller state (s, t, n) -> working words (flip count 0); adds sum of n to
 // *sum_n.

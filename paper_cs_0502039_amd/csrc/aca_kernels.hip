@@ -30,12 +30,15 @@
 // change before it applies its arrival (Fig. 3.1 and the uniqueness argument
 // that follows it).
 //
-// Work distribution.  Each wavefront scans a strided share of the region's
-// cells; enabled cells are compacted with a ballot into a per-wavefront list
-// in LDS and applied 64 at a time, so the Philox draw and the logarithm run
-// on full wavefronts.  A workgroup barrier after each sweep counts the
-// arrivals applied; the visit ends after a sweep with none or after
-// max_sweeps sweeps.
+// Work distribution.  One scan at the start of a visit lists every enabled
+// cell.  After that a cell's status can only change when it or a neighbour
+// applies an arrival, so the visit proceeds in rounds over worklists: the
+// wavefronts take the current list 64 cells at a time (the Philox draw and
+// the logarithm run on full wavefronts), and each lane then re-tests the cell
+// it applied and that cell's neighbour slots; a newly enabled cell is claimed
+// with an LDS bit (so it is listed once) and appended, with one LDS atomic
+// per wavefront, to the next round's list.  A barrier separates rounds; the
+// visit ends when a round's list is empty or after max_sweeps rounds.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,7 +52,6 @@ namespace {
 
 constexpr uint64_t kSignBit = 0x8000000000000000ull;
 constexpr uint64_t kTimeMask = 0x7FFFFFFFFFFFFFFFull;
-constexpr int kListCap = 128;   // per-wavefront list: 64 pending + 64 incoming
 
 __device__ __forceinline__ int wrap_side(int g, int side)
 {
@@ -67,39 +69,39 @@ __device__ __forceinline__ void lds_store_word(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// LDS carve-up shared with visit_lds_bytes().
+// LDS carve-up shared with visit_lds_bytes().  Per region: packed words for
+// the whole box, counts / flip deltas / claim bits for the simulated cells,
+// and two lists of cell indices (a list never holds two neighbours, so half
+// the simulated cells plus one bounds it).
 struct LdsPlan {
-    size_t thr_off, ctr_off, ts_off, n_off, f_off, list_off, total;
+    size_t thr_off, ctr_off, ts_off, n_off, f_off, claim_off, list_off, list_cap, total;
 };
 
-__host__ __device__ inline LdsPlan lds_plan(int box_max, int nwaves)
+__host__ __device__ inline LdsPlan lds_plan(int box_max, int inner_max)
 {
     LdsPlan p;
-    p.thr_off = 0;                                   // uint64 thr[16]
-    p.ctr_off = 128;                                 // int counters[8]
-    p.ts_off = 160;                                  // uint64 ts[box_max]
-    p.n_off = p.ts_off + 8 * (size_t)box_max;        // uint32 n[box_max]
-    p.f_off = p.n_off + 4 * (size_t)box_max;         // uint16 flips[box_max]
-    p.list_off = p.f_off + 2 * (size_t)box_max;      // uint32 per wave 2*kListCap
-    p.list_off = (p.list_off + 15) & ~(size_t)15;
-    p.total = p.list_off + (size_t)nwaves * 2 * kListCap * 4;
+    p.thr_off = 0;                                          // uint64 thr[16]
+    p.ctr_off = 128;                                        // int counters[16]
+    p.ts_off = 192;                                         // uint64 ts[box]
+    p.n_off = p.ts_off + 8 * (size_t)box_max;               // uint32 n[inner]
+    p.f_off = p.n_off + 4 * (size_t)inner_max;              // uint16 f[inner]
+    p.claim_off = (p.f_off + 2 * (size_t)inner_max + 3) & ~(size_t)3;
+    p.list_off = p.claim_off + 4 * (size_t)((inner_max + 31) / 32 + 2);
+    p.list_cap = (size_t)inner_max / 2 + 2;                 // uint16 list[2][cap]
+    p.total = p.list_off + 2 * 2 * p.list_cap;
+    p.total = (p.total + 15) & ~(size_t)15;
     return p;
 }
 
-__host__ __device__ inline int region_box_max(int dim, const VisitArgs &a)
+__host__ __device__ inline int region_box_max(int dim, const VisitArgs &a, int *inner_max)
 {
-    int box = 1;
+    int box = 1, inner = 1;
     for (int d = 0; d < dim; ++d) {
         const int rin = a.span[d] ? a.L[d] : a.tile[d] + 2 * a.ghost[d];
+        inner *= rin;
         box *= rin + (a.span[d] ? 0 : 2);
     }
+    if (inner_max) *inner_max = inner;
     return box;
 }
 
@@ -124,17 +126,125 @@ __global__ void aca_init_kernel(uint64_t n_cells, uint32_t key_lo, uint32_t key_
 
 // ----------------------------------------------------------------- visit
 
+// Exact quotient n / d from one high multiply with magic = ceil(2^32 / d),
+// valid for n * d < 2^32 (here n < 2^16, d < 2^16); d == 1 is passed as
+// magic == 0 and returns n.
+__device__ __forceinline__ int div_magic(int n, uint32_t magic)
+{
+    return magic ? (int)__umulhi((uint32_t)n, magic) : n;
+}
+
+__device__ __forceinline__ uint32_t magic_for(int d)
+{
+    return d > 1 ? 0xFFFFFFFFu / (uint32_t)d + 1u : 0u;
+}
+
+template <int DIM>
+struct Region {
+    int rin[3], ring[3], org[3], olo[3], ohi[3], side[3], span[3];
+    int sbox[3];          // strides of the ring box
+    uint32_t magic[2];    // for dividing by rin[0], rin[1]
+    int inner, box;
+    int gs1, gs2;         // global strides
+
+    __device__ __forceinline__ void coords(int i, int p[3]) const
+    {
+        const int r = (DIM > 1) ? div_magic(i, magic[0]) : 0;
+        p[0] = i - r * rin[0];
+        if (DIM > 2) {
+            p[2] = div_magic(r, magic[1]);
+            p[1] = r - p[2] * rin[1];
+        } else {
+            p[1] = r;
+            p[2] = 0;
+        }
+    }
+    __device__ __forceinline__ int box_index(const int p[3]) const
+    {
+        return (p[0] + ring[0]) + sbox[1] * (p[1] + ring[1]) + sbox[2] * (p[2] + ring[2]);
+    }
+    __device__ __forceinline__ int inner_index(const int p[3]) const
+    {
+        return p[0] + rin[0] * (p[1] + rin[1] * p[2]);
+    }
+    __device__ __forceinline__ int global_coord(int d, int pd) const
+    {
+        return wrap_side(org[d] + pd, side[d]);
+    }
+    __device__ __forceinline__ uint32_t global_index(const int p[3]) const
+    {
+        uint32_t g = (uint32_t)global_coord(0, p[0]);
+        if (DIM > 1) g += (uint32_t)gs1 * (uint32_t)global_coord(1, p[1]);
+        if (DIM > 2) g += (uint32_t)gs2 * (uint32_t)global_coord(2, p[2]);
+        return g;
+    }
+    // Box offsets of the +d / -d neighbours of a simulated cell at p.
+    __device__ __forceinline__ void slot_offsets(int d, const int p[3], int &up, int &dn) const
+    {
+        up = sbox[d];
+        dn = -sbox[d];
+        if (span[d]) {
+            if (p[d] == rin[d] - 1) up -= rin[d] * sbox[d];
+            if (p[d] == 0) dn += rin[d] * sbox[d];
+        }
+    }
+};
+
+// Enabling test of Fig. 3.1 for the simulated cell at p: its pending arrival
+// is before the horizon and precedes, in (time, global index) order, the
+// pending arrival of every neighbour slot.  No branches: every neighbour word
+// is loaded and the comparisons are combined bitwise.
+template <int DIM>
+__device__ __forceinline__ bool cell_enabled(const Region<DIM> &R, const uint64_t *ts,
+                                             const int p[3], int bi, uint64_t horizon)
+{
+    const uint64_t tw = lds_load_word(&ts[bi]) & kTimeMask;
+    uint64_t tn[2 * DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        int up, dn;
+        R.slot_offsets(d, p, up, dn);
+        tn[2 * d] = lds_load_word(&ts[bi + up]) & kTimeMask;
+        tn[2 * d + 1] = lds_load_word(&ts[bi + dn]) & kTimeMask;
+    }
+    bool en = tw < horizon;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        // on equal times the smaller global index goes first: the +d
+        // neighbour has the larger index unless it wraps round the lattice,
+        // the -d neighbour the smaller one unless it wraps
+        const int gd = R.global_coord(d, p[d]);
+        const bool up_ok = (tw < tn[2 * d]) | ((tw == tn[2 * d]) & (gd + 1 < R.side[d]));
+        const bool dn_ok = (tw < tn[2 * d + 1]) | ((tw == tn[2 * d + 1]) & (gd == 0));
+        en = en & up_ok & dn_ok;
+    }
+    return en;
+}
+
+// Append the cells of the lanes with `want` set to the list at `list` whose
+// length counter is *size; one LDS atomic per wavefront.
+__device__ __forceinline__ void wave_append(bool want, uint16_t value, uint16_t *list,
+                                            int *size, int lane)
+{
+    const uint64_t m = __ballot(want);
+    if (m) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(size, (int)__popcll(m));
+        base = __shfl(base, 0, 64);
+        if (want) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = value;
+    }
+}
+
 template <int DIM>
 __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
     const int nthreads = blockDim.x;
-    const int nwaves = nthreads >> 6;
 
     // ---- region geometry of this tile
+    Region<DIM> R;
     int tc[3];
     {
         uint32_t b = blockIdx.x;
@@ -143,44 +253,58 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         tc[1] = (int)(b % (uint32_t)a.ntiles[1]);
         tc[2] = (int)(b / (uint32_t)a.ntiles[1]);
     }
-    int rin[3], ring[3], rbox[3], org[3], olo[3], ohi[3], side[3];
+    int rbox[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        R.span[d] = 1;
         if (d < DIM) {
-            side[d] = a.L[d];
+            R.side[d] = a.L[d];
+            R.span[d] = a.span[d];
             const int lo = tc[d] * a.tile[d];
             const int w = min(a.tile[d], a.L[d] - lo);
             if (a.span[d]) {
-                rin[d] = a.L[d]; ring[d] = 0; org[d] = 0; olo[d] = 0; ohi[d] = a.L[d];
+                R.rin[d] = a.L[d]; R.ring[d] = 0; R.org[d] = 0; R.olo[d] = 0; R.ohi[d] = a.L[d];
             } else {
-                rin[d] = w + 2 * a.ghost[d]; ring[d] = 1; org[d] = lo - a.ghost[d];
-                olo[d] = a.ghost[d]; ohi[d] = a.ghost[d] + w;
+                R.rin[d] = w + 2 * a.ghost[d]; R.ring[d] = 1; R.org[d] = lo - a.ghost[d];
+                R.olo[d] = a.ghost[d]; R.ohi[d] = a.ghost[d] + w;
             }
         } else {
-            side[d] = 1; rin[d] = 1; ring[d] = 0; org[d] = 0; olo[d] = 0; ohi[d] = 1;
+            R.side[d] = 1; R.rin[d] = 1; R.ring[d] = 0; R.org[d] = 0; R.olo[d] = 0; R.ohi[d] = 1;
         }
-        rbox[d] = rin[d] + 2 * ring[d];
+        rbox[d] = R.rin[d] + 2 * R.ring[d];
     }
-    const int sbox[3] = {1, rbox[0], rbox[0] * rbox[1]};
-    const int inner = rin[0] * rin[1] * rin[2];
-    const int box = rbox[0] * rbox[1] * rbox[2];
-    const int gs1 = side[0], gs2 = side[0] * side[1];
+    R.sbox[0] = 1;
+    R.sbox[1] = rbox[0];
+    R.sbox[2] = rbox[0] * rbox[1];
+    R.inner = R.rin[0] * R.rin[1] * R.rin[2];
+    R.box = rbox[0] * rbox[1] * rbox[2];
+    R.gs1 = R.side[0];
+    R.gs2 = R.side[0] * R.side[1];
+    R.magic[0] = magic_for(R.rin[0]);
+    R.magic[1] = magic_for(R.rin[1]);
 
-    const LdsPlan plan = lds_plan(region_box_max(DIM, a), nwaves);
+    int inner_max = 0;
+    const int box_max = region_box_max(DIM, a, &inner_max);
+    const LdsPlan plan = lds_plan(box_max, inner_max);
     uint64_t *thr = reinterpret_cast<uint64_t *>(lds + plan.thr_off);
     int *ctr = reinterpret_cast<int *>(lds + plan.ctr_off);
     uint64_t *ts = reinterpret_cast<uint64_t *>(lds + plan.ts_off);
     uint32_t *nl = reinterpret_cast<uint32_t *>(lds + plan.n_off);
     uint16_t *fl = reinterpret_cast<uint16_t *>(lds + plan.f_off);
-    uint32_t *meta_list = reinterpret_cast<uint32_t *>(lds + plan.list_off) +
-                          wave * 2 * kListCap;
-    uint32_t *gidx_list = meta_list + kListCap;
+    uint32_t *claim = reinterpret_cast<uint32_t *>(lds + plan.claim_off);
+    uint16_t *lists = reinterpret_cast<uint16_t *>(lds + plan.list_off);
+    const int list_cap = (int)plan.list_cap;
+    // ctr[0..2] list sizes and ctr[3..5] take positions, rotating over rounds;
+    // ctr[6..9] statistics
+    int *sizes = ctr;
+    int *takes = ctr + 3;
 
     if (tid < 2 * (2 * DIM + 1)) thr[tid] = a.thr[tid];
-    if (tid < 8) ctr[tid] = 0;
+    if (tid < 16) ctr[tid] = 0;
+    for (int j = tid; j < (R.inner + 31) / 32; j += nthreads) claim[j] = 0u;
 
-    // ---- load the region (ring box) from the input state
-    for (int j = tid; j < box; j += nthreads) {
+    // ---- load the region box from the snapshot
+    for (int j = tid; j < R.box; j += nthreads) {
         int q[3];
         q[0] = j % rbox[0];
         const int r = j / rbox[0];
@@ -188,76 +312,103 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         q[2] = r / rbox[1];
         int g[3];
         bool in_core = true;
+        int pi[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            g[d] = (d < DIM) ? wrap_side(org[d] - ring[d] + q[d], side[d]) : 0;
-            in_core = in_core && q[d] >= ring[d] && q[d] < ring[d] + rin[d];
+            g[d] = (d < DIM) ? wrap_side(R.org[d] - R.ring[d] + q[d], R.side[d]) : 0;
+            pi[d] = q[d] - R.ring[d];
+            in_core = in_core && pi[d] >= 0 && pi[d] < R.rin[d];
         }
-        const uint32_t gi = (uint32_t)g[0] + (uint32_t)gs1 * (uint32_t)g[1] +
-                            (uint32_t)gs2 * (uint32_t)g[2];
+        const uint32_t gi = (uint32_t)g[0] + (uint32_t)R.gs1 * (uint32_t)g[1] +
+                            (uint32_t)R.gs2 * (uint32_t)g[2];
         const unsigned long long key = a.key_in[gi];
         ts[j] = (uint64_t)a.time_in[gi] | ((key & 1ull) << 63);
         if (in_core) {
-            nl[j] = (uint32_t)(key >> 32);
-            fl[j] = 0;
+            const int ii = R.inner_index(pi);
+            nl[ii] = (uint32_t)(key >> 32);
+            fl[ii] = 0;
         }
     }
     __syncthreads();
 
-    // ---- per-thread scan position (inner coordinates) and its stride
-    int p0[3], step[3];
-    {
-        p0[0] = tid % rin[0];
-        int r = tid / rin[0];
-        p0[1] = r % rin[1];
-        p0[2] = r / rin[1];
-        step[0] = nthreads % rin[0];
-        r = nthreads / rin[0];
-        step[1] = r % rin[1];
-        step[2] = r / rin[1];
-    }
     constexpr int Z = 2 * DIM;
     const uint64_t horizon = a.horizon_bits;
     const bool unit_rate = a.unit_rate != 0;
-
     uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
-    int sweeps = 0;
 
-    for (int sw = 0; sw < a.max_sweeps; ++sw) {
-        int cnt = 0;             // wave-uniform: entries pending in the list
-        int wave_applied = 0;    // wave-uniform
-        int p[3] = {p0[0], p0[1], p0[2]};
+    // ---- initial scan: every enabled cell, claimed, into list 0.  A
+    // wavefront's 64 lanes test 64 consecutive cells, i.e. two claim words.
+    for (int base = tid - lane; base < R.inner; base += nthreads) {
+        const int i = base + lane;
+        bool en = false;
+        if (i < R.inner) {
+            int p[3];
+            R.coords(i, p);
+            en = cell_enabled<DIM>(R, ts, p, R.box_index(p), horizon);
+            ++my_checks;
+        }
+        const uint64_t m = __ballot(en);
+        if (lane == 0 && (uint32_t)m) claim[base >> 5] = (uint32_t)m;
+        if (lane == 1 && (uint32_t)(m >> 32)) claim[(base >> 5) + 1] = (uint32_t)(m >> 32);
+        wave_append(en, (uint16_t)i, lists, &sizes[0], lane);
+    }
+    __syncthreads();
 
-        // Apply the arrivals of list entries [0, m) (m <= 64), one per lane.
-        auto apply = [&](int m) {
-            if (lane < m) {
-                const uint32_t meta = meta_list[lane];
-                const uint32_t gidx = gidx_list[lane];
-                const int bi = (int)(meta & 0xFFFFFu);
-                const bool own_cell = (meta >> 20) & 1u;
-                const uint32_t wrapf = meta >> 21;
+    // ---- rounds: apply every listed arrival; re-test the cells whose
+    // neighbourhood changed (the applied cell and its neighbour slots); claim
+    // the newly enabled ones into the next list.  A listed cell stays enabled
+    // until applied: none of its neighbours can be enabled meanwhile.
+    int rounds = 0;
+    for (int rnd = 0; rnd < a.max_sweeps; ++rnd) {
+        const int cur = rnd & 1;
+        const int sz = sizes[rnd % 3];
+        if (sz == 0) break;
+        ++rounds;
+        if (tid == 0) {
+            sizes[(rnd + 2) % 3] = 0;
+            takes[(rnd + 2) % 3] = 0;
+        }
+        const uint16_t *lcur = lists + cur * list_cap;
+        uint16_t *lnext = lists + (1 - cur) * list_cap;
+        int *next_size = &sizes[(rnd + 1) % 3];
+        for (;;) {
+            int start = 0;
+            if (lane == 0) start = atomicAdd(&takes[rnd % 3], 64);
+            start = __shfl(start, 0, 64);
+            if (start >= sz) break;
+            const bool active = lane < sz - start;
+            int p[3] = {0, 0, 0};
+            if (active) {
+                const int ii = lcur[start + lane];
+                R.coords(ii, p);
+                const int bi = R.box_index(p);
+                atomicAnd(&claim[ii >> 5], ~(1u << (ii & 31)));
                 const uint64_t wd = lds_load_word(&ts[bi]);
                 int sum = 0;
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
-                    int up = sbox[d], dn = -sbox[d];
-                    if (wrapf & (1u << (2 * d))) up -= rin[d] * sbox[d];
-                    if (wrapf & (1u << (2 * d + 1))) dn += rin[d] * sbox[d];
+                    int up, dn;
+                    R.slot_offsets(d, p, up, dn);
                     sum += (lds_load_word(&ts[bi + up]) >> 63) ? -1 : 1;
                     sum += (lds_load_word(&ts[bi + dn]) >> 63) ? -1 : 1;
                 }
-                const uint32_t k = nl[bi];
-                const Draw y = philox4x32_10(k, gidx, 0u, 0u, a.key_lo, a.key_hi);
+                const uint32_t k = nl[ii];
+                const Draw y = philox4x32_10(k, R.global_index(p), 0u, 0u, a.key_lo,
+                                             a.key_hi);
                 const int up_spin = (wd >> 63) ? 0 : 1;            // (s+1)/2
                 const int idx = (sum + Z) / 2 + (Z + 1) * up_spin;
                 const bool flip = (uint64_t)y.w2 < thr[idx];
                 const double tnow = __longlong_as_double((long long)(wd & kTimeMask));
                 const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
                 const uint64_t sign = (wd & kSignBit) ^ (flip ? kSignBit : 0ull);
-                nl[bi] = k + 1u;
-                fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
+                nl[ii] = k + 1u;
+                fl[ii] = (uint16_t)(fl[ii] + (flip ? 1u : 0u));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 lds_store_word(&ts[bi], (uint64_t)__double_as_longlong(tnext) | sign);
+                bool own_cell = true;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+                    own_cell = own_cell && p[d] >= R.olo[d] && p[d] < R.ohi[d];
                 if (own_cell) {
                     ++my_events;
                     my_flips += flip ? 1u : 0u;
@@ -265,120 +416,61 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
                     ++my_ghost;
                 }
             }
-        };
-
-        for (int base = wave * 64; base < inner; base += nthreads) {
-            const int i = base + lane;
-            bool en = false;
-            uint32_t meta = 0, gidx = 0;
-            if (i < inner) {
-                ++my_checks;
-                const int bi = (p[0] + ring[0]) + sbox[1] * (p[1] + ring[1]) +
-                               sbox[2] * (p[2] + ring[2]);
-                const uint64_t tw = lds_load_word(&ts[bi]) & kTimeMask;
-                en = tw < horizon;
-                uint32_t wrapf = 0;
-                bool own_cell = true;
-                uint32_t gi = 0;
+            // re-tests read neighbour words only after this lane's arrival is
+            // published, so the later of two concurrent re-tests of a shared
+            // neighbour sees both new words
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            // re-test the applied cell and each neighbour slot
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    int up = sbox[d], dn = -sbox[d];
-                    if (a.span[d]) {
-                        if (p[d] == rin[d] - 1) { up -= rin[d] * sbox[d]; wrapf |= 1u << (2 * d); }
-                        if (p[d] == 0) { dn += rin[d] * sbox[d]; wrapf |= 1u << (2 * d + 1); }
+            for (int slot = 0; slot <= Z; ++slot) {
+                bool want = false;
+                int ci = 0;
+                if (active) {
+                    int q[3] = {p[0], p[1], p[2]};
+                    bool inside = true;
+                    if (slot > 0) {
+                        const int d = (slot - 1) >> 1;
+                        const int step = ((slot - 1) & 1) ? -1 : 1;
+                        q[d] += step;
+                        if (R.span[d]) {
+                            q[d] = (q[d] < 0) ? q[d] + R.rin[d] : q[d];
+                            q[d] = (q[d] >= R.rin[d]) ? q[d] - R.rin[d] : q[d];
+                        } else {
+                            inside = q[d] >= 0 && q[d] < R.rin[d];
+                        }
                     }
-                    const int gd = wrap_side(org[d] + p[d], side[d]);
-                    gi += (uint32_t)gd * (uint32_t)(d == 0 ? 1 : (d == 1 ? gs1 : gs2));
-                    const uint64_t tu = lds_load_word(&ts[bi + up]) & kTimeMask;
-                    const uint64_t tdn = lds_load_word(&ts[bi + dn]) & kTimeMask;
-                    // (t, c) < (t', c'): on equal times the smaller global index
-                    // wins; +d neighbour is larger unless it wraps, -d neighbour
-                    // is smaller unless it wraps.
-                    en = en && (tw < tu || (tw == tu && gd + 1 < side[d]));
-                    en = en && (tw < tdn || (tw == tdn && gd == 0));
-                    own_cell = own_cell && p[d] >= olo[d] && p[d] < ohi[d];
+                    if (inside) {
+                        ++my_checks;
+                        ci = R.inner_index(q);
+                        if (cell_enabled<DIM>(R, ts, q, R.box_index(q), horizon)) {
+                            const uint32_t bit = 1u << (ci & 31);
+                            want = (atomicOr(&claim[ci >> 5], bit) & bit) == 0u;
+                        }
+                    }
                 }
-                meta = (uint32_t)bi | (own_cell ? (1u << 20) : 0u) | (wrapf << 21);
-                gidx = gi;
+                wave_append(want, (uint16_t)ci, lnext, next_size, lane);
             }
-            const uint64_t m = __ballot(en);
-            if (m) {
-                const int pos = cnt + (int)__popcll(m & ((1ull << lane) - 1ull));
-                if (en) {
-                    meta_list[pos] = meta;
-                    gidx_list[pos] = gidx;
-                }
-                cnt += (int)__popcll(m);
-                if (cnt >= 64) {
-                    wave_sync();
-                    apply(64);
-                    const int rest = cnt - 64;
-                    wave_sync();
-                    uint32_t mv = 0, gv = 0;
-                    if (lane < rest) {
-                        mv = meta_list[64 + lane];
-                        gv = gidx_list[64 + lane];
-                    }
-                    wave_sync();
-                    if (lane < rest) {
-                        meta_list[lane] = mv;
-                        gidx_list[lane] = gv;
-                    }
-                    wave_sync();
-                    wave_applied += 64;
-                    cnt = rest;
-                }
-            }
-            // advance the scan position by nthreads cells
-            p[0] += step[0];
-            int c = p[0] >= rin[0];
-            p[0] -= c ? rin[0] : 0;
-            p[1] += step[1] + c;
-            c = p[1] >= rin[1];
-            p[1] -= c ? rin[1] : 0;
-            p[2] += step[2] + c;
         }
-        if (cnt > 0) {
-            wave_sync();
-            apply(cnt);
-            wave_sync();
-            wave_applied += cnt;
-        }
-        if (lane == 0) atomicAdd(&ctr[sw % 3], wave_applied);
-        if (tid == 0) ctr[(sw + 1) % 3] = 0;
         __syncthreads();
-        const int total = ctr[sw % 3];
-        ++sweeps;
-        if (total == 0) break;
     }
-    __syncthreads();
 
     // ---- merge every owned copy and every ghost copy that moved into the
     // ---- next snapshot; detect owned cells with arrivals still due
     bool live = false;
-    for (int j = tid; j < inner; j += nthreads) {
+    for (int j = tid; j < R.inner; j += nthreads) {
         int p[3];
-        p[0] = j % rin[0];
-        const int r = j / rin[0];
-        p[1] = r % rin[1];
-        p[2] = r / rin[1];
-        int g[3];
+        R.coords(j, p);
         bool own_cell = true;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            g[d] = (d < DIM) ? wrap_side(org[d] + p[d], side[d]) : 0;
-            own_cell = own_cell && p[d] >= olo[d] && p[d] < ohi[d];
-        }
-        const int bi = (p[0] + ring[0]) + sbox[1] * (p[1] + ring[1]) +
-                       sbox[2] * (p[2] + ring[2]);
-        const uint32_t gi = (uint32_t)g[0] + (uint32_t)gs1 * (uint32_t)g[1] +
-                            (uint32_t)gs2 * (uint32_t)g[2];
-        const uint32_t n_copy = nl[bi];
+        for (int d = 0; d < DIM; ++d) own_cell = own_cell && p[d] >= R.olo[d] && p[d] < R.ohi[d];
+        const int bi = R.box_index(p);
+        const uint32_t gi = R.global_index(p);
+        const uint32_t n_copy = nl[j];
         const unsigned long long key_in = a.key_in[gi];
         const uint32_t n_in = (uint32_t)(key_in >> 32);
         const uint64_t wd = ts[bi];
         if (own_cell || n_copy != n_in) {
-            const unsigned long long f = ((key_in >> 1) & 0x7FFFFFFFull) + fl[bi];
+            const unsigned long long f = ((key_in >> 1) & 0x7FFFFFFFull) + fl[j];
             const unsigned long long key = ((unsigned long long)n_copy << 32) | (f << 1) |
                                            (wd >> 63);
             atomicMax(&a.key_out[gi], key);
@@ -387,18 +479,18 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         if (own_cell) live = live || (wd & kTimeMask) < horizon;
     }
     // ---- counters
-    atomicAdd(&ctr[3], (int)my_events);
-    atomicAdd(&ctr[4], (int)my_flips);
-    atomicAdd(&ctr[5], (int)my_ghost);
-    atomicAdd(&ctr[6], (int)my_checks);
+    atomicAdd(&ctr[6], (int)my_events);
+    atomicAdd(&ctr[7], (int)my_flips);
+    atomicAdd(&ctr[8], (int)my_ghost);
+    atomicAdd(&ctr[9], (int)my_checks);
     const int any_live = __syncthreads_or(live ? 1 : 0);
     if (tid == 0) {
         unsigned long long *gc = a.counters;
-        atomicAdd(&gc[kEvents], (unsigned long long)(unsigned)ctr[3]);
-        atomicAdd(&gc[kFlips], (unsigned long long)(unsigned)ctr[4]);
-        atomicAdd(&gc[kGhostEvents], (unsigned long long)(unsigned)ctr[5]);
-        atomicAdd(&gc[kChecks], (unsigned long long)(unsigned)ctr[6]);
-        atomicAdd(&gc[kSweeps], (unsigned long long)sweeps);
+        atomicAdd(&gc[kEvents], (unsigned long long)(unsigned)ctr[6]);
+        atomicAdd(&gc[kFlips], (unsigned long long)(unsigned)ctr[7]);
+        atomicAdd(&gc[kGhostEvents], (unsigned long long)(unsigned)ctr[8]);
+        atomicAdd(&gc[kChecks], (unsigned long long)(unsigned)ctr[9]);
+        atomicAdd(&gc[kSweeps], (unsigned long long)rounds);
         if (any_live) atomicAdd(&gc[kLiveTiles], 1ull);
     }
 }
@@ -482,7 +574,17 @@ unsigned grid_for(uint64_t count, unsigned block)
 
 size_t visit_lds_bytes(int dim, const VisitArgs &a, int block)
 {
-    return lds_plan(region_box_max(dim, a), block / 64).total;
+    (void)block;
+    int inner_max = 0;
+    const int box_max = region_box_max(dim, a, &inner_max);
+    return lds_plan(box_max, inner_max).total;
+}
+
+int visit_inner_max(int dim, const VisitArgs &a)
+{
+    int inner_max = 0;
+    region_box_max(dim, a, &inner_max);
+    return inner_max;
 }
 
 hipError_t launch_init(int dim, const int32_t *L, uint64_t n_cells, uint32_t key_lo,
