@@ -27,13 +27,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Plain VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64
-# instruction every 4 cycles per SIMD; FP64 add/mul run at this rate).
+# instruction every 4 cycles per SIMD; binary64 add/mul run at this rate).
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
-# Issue slots one applied arrival needs at minimum ("ALU bound"):
-# Philox4x32-10 (20 quarter-rate 32x32->64 multiplies = 80 slots, 40 xor),
-# the exponential gap (36 binary64 add/mul + the division sequence, 12 slots
-# with its quarter-rate reciprocal), flip test and clock update (8).
-SLOTS_PER_EVENT = 80 + 40 + 36 + 12 + 8
+# Issue slots one applied arrival needs at minimum on gfx950: Philox4x32-10 is
+# 20 v_mad_u64_u32 (half rate, 2 slots each) and 20 v_bitop3_b32; -ln u is 51
+# binary64 slots (16 mul, 16 add, the division sequence with its quarter-rate
+# reciprocal, conversions) and 11 integer ones; flip test and clock update 8.
+SLOTS_PER_EVENT = 40 + 20 + 51 + 11 + 8
 
 
 def log(msg: str) -> None:
@@ -44,6 +44,45 @@ def digest(s, t, n):
     return (hashlib.sha256(s.tobytes()).hexdigest(),
             hashlib.sha256(t.astype("<f8").tobytes()).hexdigest(),
             hashlib.sha256(n.astype("<u4").tobytes()).hexdigest())
+
+
+VISIT_SOURCES = ("aca_device.h", "aca_internal.h", "aca_visit_fast.hip")
+
+
+def kernel_source_digest() -> str:
+    """SHA-256 over the sources the tile-visit kernel of the large lattices is
+    compiled from."""
+    csrc = os.path.join(ROOT, "paper_cs_0502039_amd", "csrc")
+    h = hashlib.sha256()
+    for name in VISIT_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, launches: int):
+    """HBM bytes per visit launch from the committed counter summary
+    (profiles/traffic_<workload>.json, FETCH_SIZE + WRITE_SIZE scaled by a copy
+    kernel's readings), or None when it is missing or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return doc["hbm_bytes_per_launch"]
+
+
+def copy_calibration(nbytes: int = 1 << 31) -> None:
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {nbytes} bytes read and {nbytes} bytes written")
 
 
 def cpu_baseline(params: dict, T_sample: float) -> dict:
@@ -75,6 +114,8 @@ def main() -> int:
     ap.add_argument("--ghost", type=int, nargs="*", default=None)
     ap.add_argument("--sweeps", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 2 GiB device copy (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the workload is a single "
@@ -88,6 +129,8 @@ def main() -> int:
     params = getattr(workloads, args.workload)()
     T = params["T"]
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration()
     lat = aca.Lattice(params)
     if args.tile or args.ghost or args.sweeps or args.block:
         kw = {}
@@ -130,10 +173,11 @@ def main() -> int:
     ev_launch = events / launches
     alu_achieved = ev_launch / t_launch / 1e9                  # Gevents/s
     alu_peak = VALU_LANE_OPS_PER_S / SLOTS_PER_EVENT / 1e9      # Gevents/s
+    traffic = measured_traffic(args.workload, launches)
     hbm = {"bound": "hbm", "achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": hbm_achieved / HBM_PEAK_GBS, "traffic": None}
+           "frac": hbm_achieved / HBM_PEAK_GBS, "traffic": traffic}
     alu = {"bound": "alu", "achieved": alu_achieved, "peak": alu_peak,
-           "unit": "Garrivals/s", "frac": alu_achieved / alu_peak, "traffic": None}
+           "unit": "Garrivals/s", "frac": alu_achieved / alu_peak, "traffic": traffic}
     roofline = alu if alu["frac"] >= hbm["frac"] else hbm
     other = hbm if roofline is alu else alu
 

@@ -55,9 +55,10 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-// Scratch: two snapshots of working words (key, time) and the counters.
+// Scratch: two snapshots of working words (key, time), one flag byte per
+// cell for tile flags (a tile holds at least one cell), and the counters.
 struct ScratchLayout {
-    size_t key_off[2], time_off[2], ctr_off, total;
+    size_t key_off[2], time_off[2], dead_off, ctr_off, total;
 };
 
 ScratchLayout scratch_layout(uint64_t n)
@@ -70,13 +71,19 @@ ScratchLayout scratch_layout(uint64_t n)
         l.time_off[b] = off;
         off = align_up(off + 8 * n);
     }
+    l.dead_off = off;
+    off = align_up(off + n);
     l.ctr_off = off;
-    l.total = l.ctr_off + kAlign;
+    l.total = l.ctr_off + 2 * kAlign;
     return l;
 }
 
-// Counter words in scratch: the visit counters, then the pack/unpack sums.
-enum : int { kSumStart = 8, kSumEnd = 9, kSumFlips = 10, kCounterWords = 12 };
+// Counter words in scratch: two slots of visit counters (launches alternate
+// between them), the pack/unpack sums, and the two slots' block tickets.
+enum : int {
+    kSlotWords = 8, kSumStart = 16, kSumEnd = 17, kSumFlips = 18, kTicketWord = 20,
+    kCounterWords = 24
+};
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -142,13 +149,16 @@ struct aca_lattice {
     unsigned long long *key[2];     // working snapshots in scratch
     unsigned long long *time[2];
     unsigned long long *counters;   // device, in scratch
+    uint8_t *dead;                  // device, per-tile flags, in scratch
     bool initialized;
     double last_T;
     aca_tuning tun;                 // as requested (0 / -1 = automatic)
     aca_stats stats;
     uint64_t thr[14];
     int device;
-    hipEvent_t ev_start, ev_stop;
+    hipEvent_t ev_start[2], ev_stop[2];
+    unsigned long long *host_ctr;   // pinned, mapped, kCounterWords words
+    unsigned long long *host_ctr_dev;   // its device address
 };
 
 namespace {
@@ -346,6 +356,7 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
         lat->time[b] = reinterpret_cast<unsigned long long *>(sc + sl.time_off[b]);
     }
     lat->counters = reinterpret_cast<unsigned long long *>(sc + sl.ctr_off);
+    lat->dead = reinterpret_cast<uint8_t *>(sc + sl.dead_off);
     lat->initialized = false;
     lat->last_T = 0.0;
     memset(&lat->tun, 0, sizeof lat->tun);
@@ -355,10 +366,16 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
     lat->stats.struct_size = sizeof(aca_stats);
     build_thresholds(p, lat->thr);
     lat->device = dev;
-    if (hipEventCreate(&lat->ev_start) != hipSuccess ||
-        hipEventCreate(&lat->ev_stop) != hipSuccess) {
+    bool ok = hipHostMalloc((void **)&lat->host_ctr, 8 * kCounterWords,
+                            hipHostMallocMapped | hipHostMallocPortable) == hipSuccess &&
+              hipHostGetDevicePointer((void **)&lat->host_ctr_dev, lat->host_ctr, 0) ==
+                  hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipEventCreate(&lat->ev_start[i]) == hipSuccess &&
+             hipEventCreate(&lat->ev_stop[i]) == hipSuccess;
+    if (!ok) {
         delete lat;
-        return fail(ACA_EDEVICE, "hipEventCreate failed");
+        return fail(ACA_EDEVICE, "pinned host word or HIP event creation failed");
     }
     *out = lat;
     return ACA_OK;
@@ -449,61 +466,90 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
     if (plan.lds > 64 * 1024)
         HIP_TRY(plan.fast ? aca::set_visit_fast_lds_limit(plan.lds)
                           : aca::set_visit_lds_limit(plan.lds));
-    unsigned long long host_ctr[kCounterWords];
+    unsigned long long *host = lat->host_ctr;
     const uint64_t tiles = (uint64_t)plan.a.ntiles[0] * plan.a.ntiles[1] * plan.a.ntiles[2];
     const uint64_t bytes_per_launch = launch_region_bytes(lat->p.dim, plan.a);
 
     // caller state -> snapshot 0; snapshot 1 starts below every copy (zero)
-    HIP_TRY(hipMemsetAsync(lat->counters, 0, sizeof host_ctr, s));
+    HIP_TRY(hipMemsetAsync(lat->counters, 0, 8 * kCounterWords, s));
     HIP_TRY(aca::launch_pack(lat->n, lat->s, lat->t, lat->cnt, lat->key[0], lat->time[0],
                              lat->counters + kSumStart, s));
     HIP_TRY(hipMemsetAsync(lat->key[1], 0, 8 * lat->n, s));
     HIP_TRY(hipMemsetAsync(lat->time[1], 0, 8 * lat->n, s));
-    int cur = 0;
+
+    HIP_TRY(hipMemsetAsync(lat->dead, 0, tiles, s));
+
+    // Launch k reads snapshot k % 2, merges into the other one and counts
+    // into slot k % 2; its last block publishes the slot to pinned host
+    // memory.  While many tiles are live, launch k+1 is enqueued before the
+    // host waits for launch k, so the round trip overlaps a kernel; if launch
+    // k turns out to be the last one needed, launch k+1 only re-reads the
+    // final snapshot (nothing is due, so nothing changes) and is discarded.
+    auto enqueue = [&](uint64_t k) -> aca_status {
+        const int in = (int)(k & 1), out = 1 - in, slot = in;
+        plan.a.key_in = lat->key[in];
+        plan.a.time_in = lat->time[in];
+        plan.a.key_out = lat->key[out];
+        plan.a.time_out = lat->time[out];
+        plan.a.counters = lat->counters + slot * kSlotWords;
+        plan.a.host_counters = lat->host_ctr_dev + slot * kSlotWords;
+        plan.a.done_blocks = reinterpret_cast<unsigned int *>(lat->counters + kTicketWord + slot);
+        plan.a.dead = lat->dead;
+        HIP_TRY(hipEventRecord(lat->ev_start[slot], s));
+        HIP_TRY(plan.fast ? aca::launch_visit_fast(lat->p.dim, plan.a, plan.block, plan.lds, s)
+                          : aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
+        HIP_TRY(hipEventRecord(lat->ev_stop[slot], s));
+        return ACA_OK;
+    };
     // Every launch applies at least the globally earliest due arrival, so the
     // loop ends; the bound only turns a pathological schedule into an error.
     const uint64_t max_launches = 100000;
-    for (uint64_t launch = 0;; ++launch) {
-        if (launch >= max_launches)
+    aca_status est = enqueue(0);
+    if (est != ACA_OK) return est;
+    uint64_t enqueued = 1, prev_live = tiles, k = 0;
+    for (;; ++k) {
+        if (k + 1 >= max_launches)
             return fail(ACA_ENOPROGRESS, "horizon not reached after %llu launches",
-                        (unsigned long long)launch);
-        const int out = 1 - cur;
-        plan.a.key_in = lat->key[cur];
-        plan.a.time_in = lat->time[cur];
-        plan.a.key_out = lat->key[out];
-        plan.a.time_out = lat->time[out];
-        HIP_TRY(hipMemsetAsync(lat->counters, 0, 8 * aca::kNumCounters, s));
-        HIP_TRY(hipEventRecord(lat->ev_start, s));
-        HIP_TRY(plan.fast ? aca::launch_visit_fast(lat->p.dim, plan.a, plan.block, plan.lds, s)
-                          : aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
-        HIP_TRY(hipEventRecord(lat->ev_stop, s));
-        HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, 8 * aca::kNumCounters,
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+                        (unsigned long long)k + 1);
+        if (enqueued == k + 1 && prev_live * 8 > tiles) {
+            est = enqueue(k + 1);
+            if (est != ACA_OK) return est;
+            ++enqueued;
+        }
+        const int slot = (int)(k & 1);
+        HIP_TRY(hipEventSynchronize(lat->ev_stop[slot]));
+        const unsigned long long *hc = host + slot * kSlotWords;
         float kms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&kms, lat->ev_start, lat->ev_stop));
-        cur = out;
+        HIP_TRY(hipEventElapsedTime(&kms, lat->ev_start[slot], lat->ev_stop[slot]));
         aca_stats &S = lat->stats;
         S.kernel_ms += kms;
         S.region_bytes += bytes_per_launch;
         S.launches += 1;
         S.visits += tiles;
-        S.ghost_events += host_ctr[aca::kGhostEvents];
-        S.sweeps += host_ctr[aca::kSweeps];
-        S.cell_checks += host_ctr[aca::kChecks];
-        if (host_ctr[aca::kLiveTiles] == 0) break;
-        if (host_ctr[aca::kEvents] + host_ctr[aca::kGhostEvents] == 0)
+        S.ghost_events += hc[aca::kGhostEvents];
+        S.sweeps += hc[aca::kSweeps];
+        S.cell_checks += hc[aca::kChecks];
+        if (hc[aca::kLiveTiles] == 0) break;
+        if (hc[aca::kEvents] + hc[aca::kGhostEvents] == 0)
             return fail(ACA_ENOPROGRESS, "a launch applied no arrival while %llu tiles "
                         "still had arrivals before the horizon",
-                        (unsigned long long)host_ctr[aca::kLiveTiles]);
+                        (unsigned long long)hc[aca::kLiveTiles]);
+        prev_live = hc[aca::kLiveTiles];
+        if (enqueued == k + 1) {
+            est = enqueue(k + 1);
+            if (est != ACA_OK) return est;
+            ++enqueued;
+        }
     }
+    // launch k produced the final record, in snapshot (k + 1) % 2
+    const int cur = (int)((k + 1) & 1);
     HIP_TRY(aca::launch_unpack(lat->n, lat->key[cur], lat->time[cur], lat->s, lat->t,
                                lat->cnt, lat->counters + kSumEnd, s));
-    HIP_TRY(hipMemcpyAsync(host_ctr, lat->counters, sizeof host_ctr, hipMemcpyDeviceToHost,
-                           s));
+    HIP_TRY(hipMemcpyAsync(host + kSumStart, lat->counters + kSumStart, 8 * 3,
+                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    lat->stats.events += host_ctr[kSumEnd] - host_ctr[kSumStart];
-    lat->stats.flips += host_ctr[kSumFlips];
+    lat->stats.events += host[kSumEnd] - host[kSumStart];
+    lat->stats.flips += host[kSumFlips];
     lat->last_T = T;
     lat->stats.last_T = T;
     lat->stats.device_ms +=
@@ -536,8 +582,11 @@ ACA_EXPORT aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
 ACA_EXPORT aca_status aca_destroy(aca_lattice *lat)
 {
     if (lat) {
-        hipEventDestroy(lat->ev_start);
-        hipEventDestroy(lat->ev_stop);
+        for (int i = 0; i < 2; ++i) {
+            hipEventDestroy(lat->ev_start[i]);
+            hipEventDestroy(lat->ev_stop[i]);
+        }
+        hipHostFree(lat->host_ctr);
     }
     delete lat;
     return ACA_OK;

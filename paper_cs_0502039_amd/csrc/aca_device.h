@@ -15,7 +15,8 @@ namespace aca {
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The key is uniform
 // across the wavefront, so its Weyl schedule stays in scalar registers; each
-// round costs two 32x32->64 multiplies per lane.
+// round costs two 32x32->64 multiplies and two three-input XORs (gfx950's
+// v_bitop3_b32 with truth table 0x96) per lane.
 struct Draw {
     uint32_t w0, w1, w2, w3;
 };
@@ -34,8 +35,8 @@ __device__ __forceinline__ Draw philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
         const uint32_t kb = key_hi + kWeylB * (uint32_t)round;
         const uint64_t prodA = (uint64_t)kMulA * c0;
         const uint64_t prodB = (uint64_t)kMulB * c2;
-        const uint32_t n0 = (uint32_t)(prodB >> 32) ^ c1 ^ ka;
-        const uint32_t n2 = (uint32_t)(prodA >> 32) ^ c3 ^ kb;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(prodB >> 32), c1, ka, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(prodA >> 32), c3, kb, 0x96);
         c1 = (uint32_t)prodB;
         c3 = (uint32_t)prodA;
         c0 = n0;

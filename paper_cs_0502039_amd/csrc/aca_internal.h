@@ -44,9 +44,35 @@ struct VisitArgs {
     const unsigned long long *time_in;
     unsigned long long *key_out;          // merged record (element-wise max)
     unsigned long long *time_out;
-    unsigned long long *counters;
+    unsigned long long *counters;         // device slot of this launch
+    unsigned long long *host_counters;    // pinned host copy, written by the last block
+    unsigned int *done_blocks;            // ticket counter of this slot
+    uint8_t *dead;                        // per tile: owned cells final in both snapshots
     uint64_t thr[14];
 };
+
+// Called by thread 0 of every block of a visit launch after it has added its
+// counters.  The last block to finish (ticket ntiles - 1) publishes the slot's
+// counters to pinned host memory and clears the slot for its next use, so a
+// launch needs no separate memset or copy command.
+__device__ inline void finish_visit_block(const VisitArgs &a, unsigned int ntiles)
+{
+    __threadfence();
+    const unsigned int ticket = atomicAdd(a.done_blocks, 1u);
+    if (ticket == ntiles - 1u) {
+        __threadfence();
+        for (int i = 0; i < kNumCounters; ++i) {
+            const unsigned long long v =
+                __hip_atomic_load(&a.counters[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.host_counters[i], v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&a.counters[i], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __hip_atomic_store(a.done_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence_system();
+    }
+}
 
 // Bytes of dynamic LDS a visit needs for the largest region of this plan, and
 // the number of simulated cells of that region (must stay below 65536).

@@ -244,6 +244,13 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     const int nthreads = blockDim.x;
 
     // ---- region geometry of this tile
+    const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
+                                      (unsigned)a.ntiles[2];
+    // a tile whose owned cells are final in both snapshots has nothing to do
+    if (a.dead[blockIdx.x]) {
+        if (threadIdx.x == 0) finish_visit_block(a, ntiles_total);
+        return;
+    }
     Region<DIM> R;
     int tc[3];
     {
@@ -303,7 +310,9 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     if (tid < 16) ctr[tid] = 0;
     for (int j = tid; j < (R.inner + 31) / 32; j += nthreads) claim[j] = 0u;
 
-    // ---- load the region box from the snapshot
+    // ---- load the region box from the snapshot; note whether any owned
+    // cell still has an arrival before the horizon
+    bool due = false;
     for (int j = tid; j < R.box; j += nthreads) {
         int q[3];
         q[0] = j % rbox[0];
@@ -322,20 +331,28 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         const uint32_t gi = (uint32_t)g[0] + (uint32_t)R.gs1 * (uint32_t)g[1] +
                             (uint32_t)R.gs2 * (uint32_t)g[2];
         const unsigned long long key = a.key_in[gi];
-        ts[j] = (uint64_t)a.time_in[gi] | ((key & 1ull) << 63);
+        const unsigned long long tb = a.time_in[gi];
+        ts[j] = (uint64_t)tb | ((key & 1ull) << 63);
         if (in_core) {
             const int ii = R.inner_index(pi);
             nl[ii] = (uint32_t)(key >> 32);
             fl[ii] = 0;
+            bool own_cell = true;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                own_cell = own_cell && pi[d] >= R.olo[d] && pi[d] < R.ohi[d];
+            due = due || (own_cell && (uint64_t)tb < a.horizon_bits);
         }
     }
-    __syncthreads();
+    const int own_due = __syncthreads_or(due ? 1 : 0);
 
     constexpr int Z = 2 * DIM;
     const uint64_t horizon = a.horizon_bits;
     const bool unit_rate = a.unit_rate != 0;
     uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
 
+    int rounds = 0;
+    if (own_due) {
     // ---- initial scan: every enabled cell, claimed, into list 0.  A
     // wavefront's 64 lanes test 64 consecutive cells, i.e. two claim words.
     for (int base = tid - lane; base < R.inner; base += nthreads) {
@@ -358,7 +375,6 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     // neighbourhood changed (the applied cell and its neighbour slots); claim
     // the newly enabled ones into the next list.  A listed cell stays enabled
     // until applied: none of its neighbours can be enabled meanwhile.
-    int rounds = 0;
     for (int rnd = 0; rnd < a.max_sweeps; ++rnd) {
         const int cur = rnd & 1;
         const int sz = sizes[rnd % 3];
@@ -453,6 +469,7 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         }
         __syncthreads();
     }
+    }  // own_due
 
     // ---- merge every owned copy and every ghost copy that moved into the
     // ---- next snapshot; detect owned cells with arrivals still due
@@ -492,16 +509,30 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         atomicAdd(&gc[kChecks], (unsigned long long)(unsigned)ctr[9]);
         atomicAdd(&gc[kSweeps], (unsigned long long)rounds);
         if (any_live) atomicAdd(&gc[kLiveTiles], 1ull);
+        // owned cells that were all at or past the horizon when loaded can
+        // never change again: both snapshots now hold them
+        if (!own_due) a.dead[blockIdx.x] = 1;
+        finish_visit_block(a, ntiles_total);
     }
 }
 
 // ----------------------------------------------------------------- pack
 
+// Sum over the block (wavefront shuffles, then LDS), one global atomic per
+// block; called by every thread of the block.
 __device__ __forceinline__ void block_add(unsigned long long *dst, unsigned long long v)
 {
-    // wavefront reduction, then one atomic per wavefront
+    __shared__ unsigned long long part[16];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) part[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        if (t) atomicAdd(dst, t);
+    }
+    __syncthreads();
 }
 
 __global__ void pack_kernel(uint64_t n_cells, const int8_t *s, const double *t,
@@ -619,13 +650,21 @@ hipError_t launch_visit(int dim, const VisitArgs &a, int block, size_t lds,
     return hipGetLastError();
 }
 
+// Grid of at most four blocks per CU: each thread loops over many cells, so
+// the per-block sums need few global atomics.
+unsigned reduce_grid(uint64_t count, unsigned block)
+{
+    const unsigned g = grid_for(count, block);
+    return g < 1024u ? g : 1024u;
+}
+
 hipError_t launch_pack(uint64_t n_cells, const int8_t *s, const double *t,
                        const uint32_t *n, unsigned long long *key,
                        unsigned long long *time, unsigned long long *sum_n,
                        hipStream_t stream)
 {
     const unsigned block = 256;
-    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_cells, block)), dim3(block), 0, stream,
+    hipLaunchKernelGGL(pack_kernel, dim3(reduce_grid(n_cells, block)), dim3(block), 0, stream,
                        n_cells, s, t, n, key, time, sum_n);
     return hipGetLastError();
 }
@@ -635,7 +674,7 @@ hipError_t launch_unpack(uint64_t n_cells, const unsigned long long *key,
                          uint32_t *n, unsigned long long *sums, hipStream_t stream)
 {
     const unsigned block = 256;
-    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_cells, block)), dim3(block), 0,
+    hipLaunchKernelGGL(unpack_kernel, dim3(reduce_grid(n_cells, block)), dim3(block), 0,
                        stream, n_cells, key, time, s, t, n, sums);
     return hipGetLastError();
 }

@@ -40,6 +40,14 @@ __device__ __forceinline__ void stw(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Pending time of a packed word: the spin is the sign bit and every time is
+// positive, so |word as binary64| is the time (a free source modifier), and
+// binary64 order on these values is the order of their bit patterns.
+__device__ __forceinline__ double time_of(uint64_t w)
+{
+    return __builtin_fabs(__longlong_as_double((long long)w));
+}
+
 __device__ __forceinline__ int wrap_into(int g, int side)
 {
     g = (g < 0) ? g + side : g;
@@ -136,6 +144,13 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
     const int lane = tid & 63;
     const int nthreads = blockDim.x;
 
+    const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
+                                      (unsigned)a.ntiles[2];
+    // a tile whose owned cells are final in both snapshots has nothing to do
+    if (a.dead[blockIdx.x]) {
+        if (threadIdx.x == 0) finish_visit_block(a, ntiles_total);
+        return;
+    }
     // ---- geometry: box coordinates 0..rin+1 (ring at both ends) per axis
     int tc[3];
     {
@@ -195,7 +210,9 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
     for (int j = tid; j < (boxp + 31) / 32; j += nthreads) claim[j] = 0u;
     __syncthreads();
 
-    // ---- load the region box from the snapshot
+    // ---- load the region box from the snapshot; note whether any owned
+    // cell still has an arrival before the horizon
+    bool due = false;
     const int nbox = rb[0] * rb[1] * rb[2];
     for (int j = tid; j < nbox; j += nthreads) {
         const int q0 = j % rb[0];
@@ -205,18 +222,24 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
         const int bi = q0 + P1 * q1 + P12 * q2;
         const uint32_t gi = tx[q0] + ty[q1] + tz[q2];
         const unsigned long long key = a.key_in[gi];
-        ts[bi] = (uint64_t)a.time_in[gi] | ((key & 1ull) << 63);
+        const unsigned long long tb = a.time_in[gi];
+        ts[bi] = (uint64_t)tb | ((key & 1ull) << 63);
         const bool in0 = q0 >= 1 && q0 <= rin[0];
         const bool in1 = DIM < 2 || (q1 >= 1 && q1 <= rin[1]);
         const bool in2 = DIM < 3 || (q2 >= 1 && q2 <= rin[2]);
         if (in0 && in1 && in2) {
             nl[bi] = (uint32_t)(key >> 32);
             fl[bi] = 0;
+            const bool own = q0 >= olo[0] && q0 < ohi[0] &&
+                             (DIM < 2 || (q1 >= olo[1] && q1 < ohi[1])) &&
+                             (DIM < 3 || (q2 >= olo[2] && q2 < ohi[2]));
+            due = due || (own && (uint64_t)tb < a.horizon_bits);
         }
     }
-    __syncthreads();
+    const int own_due = __syncthreads_or(due ? 1 : 0);
 
     const uint64_t horizon = a.horizon_bits;
+    const double horizon_t = __longlong_as_double((long long)a.horizon_bits);
     const bool unit_rate = a.unit_rate != 0;
     uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
 
@@ -242,6 +265,8 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
         return en;
     };
 
+    int rounds = 0;
+    if (own_due) {
     // ---- initial scan: every enabled simulated cell, claimed, into list 0
     for (int base = tid - lane; base < inner; base += nthreads) {
         const int i = base + lane;
@@ -254,17 +279,23 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
             q[1] = (DIM > 1) ? r % rin[1] + 1 : 0;
             q[2] = (DIM > 2) ? r / rin[1] + 1 : 0;
             bi = q[0] + P1 * q[1] + P12 * q[2];
-            const uint64_t tc = ldw(&ts[bi]) & kMask;
+            const uint64_t wc = ldw(&ts[bi]);
             uint64_t tn[Z];
-            bool lt = true, le = true;
+            double tmin = time_of(ldw(&ts[bi + off(1)]));
+            tn[0] = 0;
 #pragma unroll
             for (int j = 0; j < Z; ++j) {
-                tn[j] = ldw(&ts[bi + off(1 + j)]) & kMask;
-                lt = lt && tc < tn[j];
-                le = le && tc <= tn[j];
+                tn[j] = ldw(&ts[bi + off(1 + j)]);
+                if (j) tmin = __builtin_fmin(tmin, time_of(tn[j]));
             }
-            en = (tc < horizon) && lt;
-            if (!lt && le && tc < horizon) en = exact(tc, tn, q);
+            const double tc = time_of(wc);
+            const bool due = tc < horizon_t;
+            en = due && tc < tmin;
+            if (due && tc == tmin) {
+#pragma unroll
+                for (int j = 0; j < Z; ++j) tn[j] &= kMask;
+                en = exact(wc & kMask, tn, q);
+            }
             ++my_checks;
             if (en) atomicOr(&claim[bi >> 5], 1u << (bi & 31));
         }
@@ -279,7 +310,6 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
     __syncthreads();
 
     // ---- worklist rounds
-    int rounds = 0;
     for (int rnd = 0; rnd < a.max_sweeps; ++rnd) {
         const int sz = sizes[rnd % 3];
         if (sz == 0) break;
@@ -357,7 +387,9 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
                     W[k] = ldw(&ts[at]);
                 }
             }
-            // re-test the applied cell (s = 0) and its neighbours (s = 1..Z)
+            // re-test the applied cell (s = 0) and its neighbours (s = 1..Z):
+            // enabled when its time is below the horizon and below the least
+            // neighbour time; equal to it only on a tie of binary64 times
             bool want[Z + 1];
             bool tie[Z + 1];
             bool any_tie = false;
@@ -369,17 +401,13 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
                     const int qs = q[ax] + (((s - 1) & 1) ? -1 : 1);
                     inside = inside && qs >= 1 && qs <= rin[ax];
                 }
-                const uint64_t tc = W[s] & kMask;
-                bool lt = true, le = true;
+                const double tc = time_of(W[s]);
+                double tmin = time_of(W[S.nb[s][0]]);
 #pragma unroll
-                for (int j = 0; j < Z; ++j) {
-                    const uint64_t tn = W[S.nb[s][j]] & kMask;
-                    lt = lt && tc < tn;
-                    le = le && tc <= tn;
-                }
-                const bool live = inside && tc < horizon;
-                want[s] = live && lt;
-                tie[s] = live && !lt && le;
+                for (int j = 1; j < Z; ++j) tmin = __builtin_fmin(tmin, time_of(W[S.nb[s][j]]));
+                const bool live = inside && tc < horizon_t;
+                want[s] = live && tc < tmin;
+                tie[s] = live && tc == tmin;
                 any_tie = any_tie || tie[s];
                 my_checks += inside ? 1u : 0u;
             }
@@ -428,6 +456,7 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
         }
         __syncthreads();
     }
+    }  // own_due
 
     // ---- merge owned copies and moved ghost copies; find due owned cells
     bool live = false;
@@ -465,6 +494,10 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
         atomicAdd(&gc[kChecks], (unsigned long long)(unsigned)ctr[9]);
         atomicAdd(&gc[kSweeps], (unsigned long long)rounds);
         if (any_live) atomicAdd(&gc[kLiveTiles], 1ull);
+        // owned cells that were all at or past the horizon when loaded can
+        // never change again: both snapshots now hold them
+        if (!own_due) a.dead[blockIdx.x] = 1;
+        finish_visit_block(a, ntiles_total);
     }
 }
 
