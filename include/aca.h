@@ -169,6 +169,104 @@ aca_status aca_philox(const uint32_t *d_ctr, uint64_t seed, uint32_t *d_out,
 aca_status aca_neg_log(const uint64_t *d_w, double *d_out, uint64_t count,
                        void *stream);
 
+
+/* ------------------------------------------------------------------ batches
+ *
+ * A batch advances many independent lattices -- any mix of dimensions,
+ * sizes, parameters and horizons -- in persistent launches that keep every
+ * compute unit busy with (lattice, tile) items.  Each lattice advances in
+ * epochs, one visit of each of its tiles per epoch, exactly as in the
+ * launches of aca_advance; the epochs of different lattices overlap, and a
+ * lattice's next epoch opens as soon as its last tile is done.  Every result
+ * is bit-identical to aca_advance of that lattice alone (the trajectory is
+ * unique, argument after Fig. 3.1; the aggregation is partition-invariant,
+ * Fig. 3.4).  Member lattices are split into at least two tiles along every
+ * direction.
+ *
+ * A batch is either driven whole (aca_batch_advance) or step by step for
+ * continuous batching: aca_batch_attach adds a lattice between steps,
+ * aca_batch_step runs one persistent launch for at most a time budget,
+ * aca_batch_poll returns the lattices that reached their horizon (their
+ * state is then in their own buffers and they are detached).  While
+ * attached, a lattice's state lives in its scratch; aca_advance, aca_read,
+ * aca_set_tuning, aca_init, aca_resume and aca_destroy on it return
+ * ACA_ESTATE.  One batch is driven from one host thread.
+ */
+typedef struct aca_batch aca_batch;   /* opaque host handle */
+
+/* Counters accumulated since aca_batch_create. */
+typedef struct aca_batch_stats {
+    uint32_t struct_size;
+    uint32_t pad_;
+    uint64_t steps;          /* persistent launches */
+    uint64_t epochs;         /* lattice epochs completed */
+    uint64_t visits;         /* tile visits (epochs times tiles) */
+    uint64_t sweeps;         /* worklist rounds summed over tile visits */
+    uint64_t events;         /* arrivals applied, exact, over finished lattices */
+    uint64_t flips;          /* of which reversed the spin, exact */
+    uint64_t ghost_events;   /* arrivals applied to ghost copies */
+    uint64_t cell_checks;    /* enabling tests evaluated */
+    uint64_t finished;       /* lattices that reached their horizon */
+    double device_ms;        /* wall time inside aca_batch_step (ms) */
+    double kernel_ms;        /* persistent visit-kernel time, HIP events (ms) */
+    uint64_t region_bytes;   /* 16 B per region cell in and per owned cell out,
+                                summed over completed epochs */
+} aca_batch_stats;
+
+/* Bytes of device work buffer for a batch of up to `capacity` lattices
+ * (descriptors, device-resident member state, work lists). */
+aca_status aca_batch_query(int32_t capacity, uint64_t *work_bytes);
+
+/* Create a batch over a caller-owned, 256-byte aligned device buffer of
+ * work_bytes >= aca_batch_query's value (on the current device; members
+ * must live on it too).  The batch owns none of the caller's memory. */
+aca_status aca_batch_create(int32_t capacity, void *d_work, uint64_t work_bytes,
+                            aca_batch **out);
+
+/* Tile shape, ghost width and worklist rounds per visit used for members of
+ * dimension `dim` attached from now on (NULL: automatic).  Per direction the
+ * lattice is cut into max(2, ceil(L / tile)) nearly equal tiles.  `block` is
+ * ignored (the persistent kernel runs 512 threads per workgroup). */
+aca_status aca_batch_set_tuning(aca_batch *b, int32_t dim, const aca_tuning *t);
+aca_status aca_batch_get_tuning(const aca_batch *b, int32_t dim, aca_tuning *out);
+
+/* Add an initialised lattice that is not a member of any batch, to be
+ * advanced to horizon T (finite, >= its last horizon).  It joins at the next
+ * step.  ACA_ENOMEM when the batch is full. */
+aca_status aca_batch_attach(aca_batch *b, aca_lattice *lat, double T);
+
+/* One persistent launch over the members: new members are packed; every
+ * member runs epochs until it reaches its horizon, or, once `budget_ms` of
+ * device time has passed (<= 0: no limit) or it has completed `max_epochs`
+ * epochs in this launch (<= 0: no limit), pauses at its next epoch boundary
+ * and resumes at the next step.  Members that reached their horizon are
+ * unpacked into their buffers and queued for aca_batch_poll.  Synchronous.
+ * *n_members (may be NULL) receives the number of members still attached.
+ * ACA_ENOPROGRESS if a member's epoch applied no arrival while arrivals were
+ * due; that member is detached with its buffers as they were at attach. */
+aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max_epochs,
+                          void *stream, int32_t *n_members);
+
+/* Pop up to cap lattices that reached their horizon, in completion order. */
+aca_status aca_batch_poll(aca_batch *b, aca_lattice **done, int32_t cap,
+                          int32_t *n_done);
+
+/* Advance lats[i] to T[i] for i < count in one batch (which must have no
+ * members), stepping until all are done; returns with every state in its
+ * buffers and the finished queue empty. */
+aca_status aca_batch_advance(aca_batch *b, aca_lattice *const *lats, const double *T,
+                             int32_t count, void *stream);
+
+/* The current members, up to cap of them, in slot order (*n_members gets
+ * their total number). */
+aca_status aca_batch_members(const aca_batch *b, aca_lattice **out, int32_t cap,
+                             int32_t *n_members);
+
+aca_status aca_batch_get_stats(const aca_batch *b, aca_batch_stats *out);
+
+/* Release the handle; ACA_ESTATE while it has members. */
+aca_status aca_batch_destroy(aca_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,10 @@ INITS = {"random": 0, "plus": 1, "minus": 2}
 EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_create", "aca_set_tuning", "aca_get_tuning", "aca_init", "aca_resume",
             "aca_advance", "aca_get_stats", "aca_read", "aca_destroy", "aca_philox",
-            "aca_neg_log")
+            "aca_neg_log", "aca_batch_query", "aca_batch_create", "aca_batch_set_tuning",
+            "aca_batch_get_tuning", "aca_batch_attach", "aca_batch_step", "aca_batch_poll",
+            "aca_batch_advance", "aca_batch_members", "aca_batch_get_stats",
+            "aca_batch_destroy")
 
 
 class AcaError(RuntimeError):
@@ -53,6 +56,16 @@ class Stats(ctypes.Structure):
                 ("cell_checks", ctypes.c_uint64), ("last_T", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("region_bytes", ctypes.c_uint64)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("steps", ctypes.c_uint64), ("epochs", ctypes.c_uint64),
+                ("visits", ctypes.c_uint64), ("sweeps", ctypes.c_uint64),
+                ("events", ctypes.c_uint64), ("flips", ctypes.c_uint64),
+                ("ghost_events", ctypes.c_uint64), ("cell_checks", ctypes.c_uint64),
+                ("finished", ctypes.c_uint64), ("device_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("region_bytes", ctypes.c_uint64)]
 
 
 _LIB = None
@@ -87,6 +100,17 @@ def load() -> ctypes.CDLL:
         "aca_destroy": [P],
         "aca_philox": [P, u64, P, u64, P],
         "aca_neg_log": [P, P, u64, P],
+        "aca_batch_query": [i32, P],
+        "aca_batch_create": [i32, P, u64, P],
+        "aca_batch_set_tuning": [P, i32, pt],
+        "aca_batch_get_tuning": [P, i32, pt],
+        "aca_batch_attach": [P, P, f64],
+        "aca_batch_step": [P, f64, i32, P, P],
+        "aca_batch_poll": [P, P, i32, P],
+        "aca_batch_advance": [P, P, P, i32, P],
+        "aca_batch_members": [P, P, i32, P],
+        "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
+        "aca_batch_destroy": [P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -213,6 +237,114 @@ class Lattice:
     def close(self) -> None:
         if getattr(self, "_h", None):
             self.lib.aca_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many lattices advanced together by the persistent batch kernel.
+
+    Attached ``Lattice`` objects are kept alive by the batch until they are
+    returned by ``poll`` (or ``advance`` returns), since the device works on
+    their buffers meanwhile.
+    """
+
+    def __init__(self, capacity: int, device: str = "cuda", stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.capacity = int(capacity)
+        nbytes = ctypes.c_uint64(0)
+        _check(self.lib.aca_batch_query(self.capacity, ctypes.byref(nbytes)))
+        self.work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib.aca_batch_create(self.capacity, self.work.data_ptr(),
+                                         int(nbytes.value), ctypes.byref(h)))
+        self._h = h
+        self._members: dict[int, "Lattice"] = {}
+
+    def _s(self) -> int:
+        return _stream_ptr(self._torch, self.stream)
+
+    def set_tuning(self, dim: int, **kw) -> None:
+        t = make_tuning(**kw) if kw else None
+        _check(self.lib.aca_batch_set_tuning(self._h, int(dim),
+                                             ctypes.byref(t) if t is not None else None))
+
+    def tuning(self, dim: int) -> dict:
+        t = Tuning()
+        _check(self.lib.aca_batch_get_tuning(self._h, int(dim), ctypes.byref(t)))
+        return {"tile": list(t.tile), "ghost": list(t.ghost), "max_sweeps": t.max_sweeps,
+                "block": t.block}
+
+    def attach(self, lat: "Lattice", T: float) -> None:
+        _check(self.lib.aca_batch_attach(self._h, lat._h, float(T)))
+        self._members[lat._h.value] = lat
+
+    def step(self, budget_ms: float = 0.0, max_epochs: int = 0) -> int:
+        """One persistent launch; returns the number of members still attached."""
+        left = ctypes.c_int32(0)
+        code = self.lib.aca_batch_step(self._h, float(budget_ms), int(max_epochs), self._s(),
+                                       ctypes.byref(left))
+        if code != ACA_OK:
+            msg = self.lib.aca_last_error().decode(errors="replace")
+            self._forget_detached()
+            raise AcaError(code, msg)
+        return int(left.value)
+
+    def _forget_detached(self) -> None:
+        buf = (ctypes.c_void_p * max(1, self.capacity))()
+        n = ctypes.c_int32(0)
+        _check(self.lib.aca_batch_members(self._h, buf, self.capacity, ctypes.byref(n)))
+        keep = {buf[i] for i in range(n.value)}
+        for key in list(self._members):
+            if key not in keep:
+                del self._members[key]
+
+    def poll(self) -> list:
+        """Lattices that reached their horizon since the last poll."""
+        out = []
+        buf = (ctypes.c_void_p * 64)()
+        n = ctypes.c_int32(0)
+        while True:
+            _check(self.lib.aca_batch_poll(self._h, buf, 64, ctypes.byref(n)))
+            for i in range(n.value):
+                out.append(self._members.pop(buf[i]))
+            if n.value < 64:
+                return out
+
+    def advance(self, lattices, T) -> None:
+        """Advance lattices[i] to T[i] in one batch (which must be empty)."""
+        lats = list(lattices)
+        Ts = np.asarray(T, dtype=np.float64)
+        if Ts.shape != (len(lats),):
+            raise ValueError("one horizon per lattice")
+        handles = (ctypes.c_void_p * max(1, len(lats)))(*[l._h.value for l in lats])
+        for l in lats:
+            self._members[l._h.value] = l
+        try:
+            _check(self.lib.aca_batch_advance(self._h, handles, Ts.ctypes.data, len(lats),
+                                              self._s()))
+        finally:
+            for l in lats:
+                self._members.pop(l._h.value, None)
+
+    def stats(self) -> dict:
+        st = BatchStats()
+        st.struct_size = ctypes.sizeof(BatchStats)
+        _check(self.lib.aca_batch_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in BatchStats._fields_
+                if k not in ("struct_size", "pad_")}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(self.lib.aca_batch_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -24,15 +24,15 @@
 #include <string>
 
 #include "../../include/aca.h"
+#include "aca_host.h"
 #include "aca_internal.h"
 
-#define ACA_EXPORT extern "C" __attribute__((visibility("default")))
+using namespace aca_host;
 
-namespace {
+namespace aca_host {
 
 thread_local std::string g_error;
 
-aca_status fail(aca_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 aca_status fail(aca_status code, const char *fmt, ...)
 {
     char buf[512];
@@ -43,23 +43,6 @@ aca_status fail(aca_status code, const char *fmt, ...)
     g_error = buf;
     return code;
 }
-
-#define HIP_TRY(expr)                                                              \
-    do {                                                                           \
-        hipError_t e_ = (expr);                                                    \
-        if (e_ != hipSuccess)                                                      \
-            return fail(ACA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
-
-// Scratch: two snapshots of working words (key, time), one flag byte per
-// cell for tile flags (a tile holds at least one cell), and the counters.
-struct ScratchLayout {
-    size_t key_off[2], time_off[2], dead_off, ctr_off, total;
-};
 
 ScratchLayout scratch_layout(uint64_t n)
 {
@@ -77,13 +60,6 @@ ScratchLayout scratch_layout(uint64_t n)
     l.total = l.ctr_off + 2 * kAlign;
     return l;
 }
-
-// Counter words in scratch: two slots of visit counters (launches alternate
-// between them), the pack/unpack sums, and the two slots' block tickets.
-enum : int {
-    kSlotWords = 8, kSumStart = 16, kSumEnd = 17, kSumFlips = 18, kTicketWord = 20,
-    kCounterWords = 24
-};
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -138,38 +114,6 @@ int build_thresholds(const aca_params *p, uint64_t *thr)
     return 2 * (z + 1);
 }
 
-}  // namespace
-
-struct aca_lattice {
-    aca_params p;
-    uint64_t n;
-    int8_t *s;                      // caller's state buffers
-    double *t;
-    uint32_t *cnt;
-    unsigned long long *key[2];     // working snapshots in scratch
-    unsigned long long *time[2];
-    unsigned long long *counters;   // device, in scratch
-    uint8_t *dead;                  // device, per-tile flags, in scratch
-    bool initialized;
-    double last_T;
-    aca_tuning tun;                 // as requested (0 / -1 = automatic)
-    aca_stats stats;
-    uint64_t thr[14];
-    int device;
-    hipEvent_t ev_start[2], ev_stop[2];
-    unsigned long long *host_ctr;   // pinned, mapped, kCounterWords words
-    unsigned long long *host_ctr_dev;   // its device address
-};
-
-namespace {
-
-struct Plan {
-    aca::VisitArgs a;
-    int block;
-    size_t lds;
-    bool fast;      // no direction spanned: the pitched-box kernel
-};
-
 // Automatic schedule knobs; every choice gives the same result.
 void auto_tuning(const aca_params &p, aca_tuning *t)
 {
@@ -181,9 +125,9 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->ghost[0] = 4; t->ghost[1] = 4;
         t->max_sweeps = 32; t->block = 512;
     } else {
-        t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 8;
-        t->ghost[0] = 2; t->ghost[1] = 2; t->ghost[2] = 2;
-        t->max_sweeps = 256; t->block = 512;
+        t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 16;
+        t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
+        t->max_sweeps = 16; t->block = 512;
     }
 }
 
@@ -291,7 +235,7 @@ uint64_t launch_region_bytes(int dim, const aca::VisitArgs &a)
     return total;
 }
 
-}  // namespace
+}  // namespace aca_host
 
 ACA_EXPORT uint32_t aca_abi_version(void) { return ACA_ABI_VERSION; }
 
@@ -358,6 +302,7 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
     lat->counters = reinterpret_cast<unsigned long long *>(sc + sl.ctr_off);
     lat->dead = reinterpret_cast<uint8_t *>(sc + sl.dead_off);
     lat->initialized = false;
+    lat->attached = false;
     lat->last_T = 0.0;
     memset(&lat->tun, 0, sizeof lat->tun);
     lat->tun.struct_size = sizeof(aca_tuning);
@@ -384,6 +329,7 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
 ACA_EXPORT aca_status aca_set_tuning(aca_lattice *lat, const aca_tuning *t)
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     aca_tuning v;
     memset(&v, 0, sizeof v);
     v.struct_size = sizeof v;
@@ -422,6 +368,7 @@ ACA_EXPORT aca_status aca_get_tuning(const aca_lattice *lat, aca_tuning *out)
 ACA_EXPORT aca_status aca_init(aca_lattice *lat, void *stream)
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(aca::launch_init(lat->p.dim, lat->p.L, lat->n, (uint32_t)lat->p.seed,
                              (uint32_t)(lat->p.seed >> 32), lat->p.rate, lat->p.init,
@@ -436,6 +383,7 @@ ACA_EXPORT aca_status aca_init(aca_lattice *lat, void *stream)
 ACA_EXPORT aca_status aca_resume(aca_lattice *lat, double T_done)
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     if (!is_finite(T_done) || T_done < 0.0)
         return fail(ACA_EINVAL, "T_done must be finite and >= 0");
     lat->initialized = true;
@@ -449,6 +397,7 @@ ACA_EXPORT aca_status aca_resume(aca_lattice *lat, double T_done)
 ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     if (!lat->initialized) return fail(ACA_ESTATE, "aca_init (or aca_resume) first");
     if (!is_finite(T)) return fail(ACA_EINVAL, "horizon must be finite");
     if (T < lat->last_T)
@@ -569,6 +518,7 @@ ACA_EXPORT aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
                                uint32_t *h_count, void *stream)
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (h_spin) HIP_TRY(hipMemcpyAsync(h_spin, lat->s, lat->n, hipMemcpyDeviceToHost, s));
     if (h_time)
@@ -581,12 +531,13 @@ ACA_EXPORT aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
 
 ACA_EXPORT aca_status aca_destroy(aca_lattice *lat)
 {
+    if (lat && lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     if (lat) {
         for (int i = 0; i < 2; ++i) {
-            hipEventDestroy(lat->ev_start[i]);
-            hipEventDestroy(lat->ev_stop[i]);
+            (void)hipEventDestroy(lat->ev_start[i]);
+            (void)hipEventDestroy(lat->ev_stop[i]);
         }
-        hipHostFree(lat->host_ctr);
+        (void)hipHostFree(lat->host_ctr);
     }
     delete lat;
     return ACA_OK;

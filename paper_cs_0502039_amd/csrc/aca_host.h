@@ -1,0 +1,87 @@
+// aca_host.h -- host-side internals shared by the C-ABI translation units:
+// error reporting, argument checks, the scratch layout, the lattice handle
+// and the tile plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/aca.h"
+#include "aca_internal.h"
+
+#define ACA_EXPORT extern "C" __attribute__((visibility("default")))
+
+// Returns ACA_EDEVICE with the HIP message from the enclosing function.
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return aca_host::fail(ACA_EDEVICE, "%s failed: %s", #expr,             \
+                                  hipGetErrorString(e_));                          \
+    } while (0)
+
+namespace aca_host {
+
+// Sets the calling thread's message (aca_last_error) and returns `code`.
+aca_status fail(aca_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Scratch: two snapshots of working words (key, time), one flag byte per
+// cell for tile flags (a tile holds at least one cell), and the counters.
+struct ScratchLayout {
+    size_t key_off[2], time_off[2], dead_off, ctr_off, total;
+};
+ScratchLayout scratch_layout(uint64_t n);
+
+// Counter words in scratch: two slots of visit counters (launches alternate
+// between them), the pack/unpack sums, and the two slots' block tickets.
+enum : int {
+    kSlotWords = 8, kSumStart = 16, kSumEnd = 17, kSumFlips = 18, kTicketWord = 20,
+    kCounterWords = 24
+};
+
+bool is_finite(double v);
+aca_status check_params(const aca_params *p, uint64_t *n_out);
+int build_thresholds(const aca_params *p, uint64_t *thr);
+
+struct Plan {
+    aca::VisitArgs a;
+    int block;
+    size_t lds;
+    bool fast;      // no direction spanned: the pitched-box kernel
+};
+
+void auto_tuning(const aca_params &p, aca_tuning *t);
+uint64_t launch_region_bytes(int dim, const aca::VisitArgs &a);
+
+}  // namespace aca_host
+
+struct aca_lattice {
+    aca_params p;
+    uint64_t n;
+    int8_t *s;                      // caller's state buffers
+    double *t;
+    uint32_t *cnt;
+    unsigned long long *key[2];     // working snapshots in scratch
+    unsigned long long *time[2];
+    unsigned long long *counters;   // device, in scratch
+    uint8_t *dead;                  // device, per-tile flags, in scratch
+    bool initialized;
+    double last_T;
+    aca_tuning tun;                 // as requested (0 / -1 = automatic)
+    aca_stats stats;
+    uint64_t thr[14];
+    int device;
+    hipEvent_t ev_start[2], ev_stop[2];
+    unsigned long long *host_ctr;   // pinned, mapped, kCounterWords words
+    unsigned long long *host_ctr_dev;   // its device address
+    bool attached;                  // member of a batch: advanced by it only
+};
+
+namespace aca_host {
+aca_status make_plan(const aca_lattice *lat, double T, Plan *plan);
+}

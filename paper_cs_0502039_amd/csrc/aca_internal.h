@@ -113,4 +113,92 @@ hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out,
 hipError_t launch_neg_log(const uint64_t *w, double *out, uint64_t count,
                           hipStream_t stream);
 
+
+// ---------------------------------------------------------------- batches
+//
+// A batch advances many independent lattices in one persistent launch.  A
+// lattice advances in epochs: epoch e visits every tile of the lattice once,
+// reading snapshot e % 2 and merging into the other one, exactly like one
+// launch of the single-lattice loop; the epochs of different lattices overlap
+// freely.  Workgroups take (lattice, tile) items from the lattices' claim
+// words; the workgroup that finishes the last tile of an epoch opens the next
+// epoch, or retires the lattice once no owned cell has an arrival before its
+// horizon.
+
+// Read-only description of one member lattice during a launch.
+struct BatchSlot {
+    VisitArgs a;                         // geometry, stream key, horizon, thresholds
+    unsigned long long *key[2];          // the two snapshots
+    unsigned long long *time[2];
+    int8_t *s;                           // the caller's state buffers
+    double *t;
+    uint32_t *cnt;
+    uint64_t n_cells;
+    int32_t dim;
+    uint32_t ntiles;
+};
+
+enum SlotStatus : uint32_t {
+    kSlotIdle = 0,      // not a member
+    kSlotRunning = 1,   // has an open epoch in this launch
+    kSlotPaused = 2,    // stopped at an epoch boundary (step budget); resumes next launch
+    kSlotDone = 3,      // horizon reached; final state in snapshot `final_snap`
+    kSlotStalled = 4,   // an epoch applied no arrival while some were due (error)
+};
+
+// Closed claim word: the low half is far above any tile count, so late
+// increments by workgroups that read an open word never reach the epoch bits.
+constexpr uint32_t kClaimClosed = 0x80000000u;
+
+// Device-resident state of one member, kept across launches.
+struct BatchState {
+    unsigned long long claim;     // epoch << 32 | tiles handed out in that epoch
+    uint32_t finished;            // tiles of the open epoch finished
+    uint32_t live;                // of which an owned cell is still before the horizon
+    uint32_t status;              // SlotStatus
+    uint32_t epochs;              // epochs completed in the current launch
+    uint32_t total_epochs;        // since the lattice joined
+    uint32_t final_snap;          // snapshot holding the final state (when done)
+    unsigned long long epoch_moves;   // arrivals applied (owned + ghost) in the open epoch
+    unsigned long long ctr[kNumCounters];   // Counter totals since the lattice joined
+    unsigned long long sum_start;   // sum of n when packed
+    unsigned long long sum_end;     // sum of n when unpacked
+    unsigned long long sum_flips;   // flips since packed (from the unpacked words)
+    unsigned long long unpacked;    // 1 once the final state is in the caller's buffers
+};
+
+struct BatchGlobal {
+    uint32_t active;              // members running in this launch
+    uint32_t error;               // a workgroup gave up waiting (no progress anywhere)
+    uint32_t pad[2];
+    unsigned long long deadline;  // device wall clock after which epochs pause
+    unsigned long long max_epochs;   // epochs per member per launch
+};
+
+// Host side of the batch kernels (aca_batch.hip).
+size_t batch_lds_bytes(int dim, const VisitArgs &a);
+hipError_t set_batch_lds_limit(size_t bytes);
+int batch_block_size();
+// Resident blocks of the visit kernel for `dim` (0 = mixed) on this device.
+hipError_t batch_max_blocks(int dim, size_t lds, int *blocks);
+// Pack the members listed in `joining` (state zeroed, snapshot 1 and tile
+// flags cleared, sum of n recorded); `block_start[i]` is the first block of
+// joining[i], block_start[count] the grid size.
+hipError_t launch_batch_pack(const BatchSlot *slots, BatchState *state,
+                             const uint32_t *joining, const uint32_t *block_start,
+                             uint32_t count, uint32_t blocks, hipStream_t stream);
+// Re-open paused members, count running ones, arm the deadline (ticks of the
+// device wall clock from now; 0 = none).
+hipError_t launch_batch_open(BatchState *state, const uint32_t *members, uint32_t count,
+                             BatchGlobal *g, unsigned long long budget_ticks,
+                             unsigned long long max_epochs, hipStream_t stream);
+hipError_t launch_batch_visit(int dim, const BatchSlot *slots, BatchState *state,
+                              const uint32_t *order, uint32_t norder, BatchGlobal *g,
+                              unsigned long long wait_limit_ticks, int blocks, size_t lds,
+                              hipStream_t stream);
+// Unpack members that are done and not yet unpacked (same block map as pack).
+hipError_t launch_batch_unpack(const BatchSlot *slots, BatchState *state,
+                               const uint32_t *members, const uint32_t *block_start,
+                               uint32_t count, uint32_t blocks, hipStream_t stream);
+
 }  // namespace aca

@@ -1,509 +1,45 @@
-// aca_visit_fast.hip -- tile visit for tiles that span no lattice direction.
+// aca_visit_fast.hip -- one launch visits every tile of one lattice once.
 //
-// Same schedule and the same results as the generic visit kernel (see
-// aca_kernels.hip for the region layout, the merge and the worklist
-// rounds); this variant is laid out for speed on the large lattices, where
-// every region has a frozen ring on all sides:
-//
-//  * LDS holds the region box with fixed pitches (the largest box of the
-//    launch), so the neighbours of a cell are constant index offsets and the
-//    worklists store box indices directly;
-//  * after applying an arrival a lane loads the cell's whole second-order
-//    neighbourhood once -- 13 words in 2D, 25 in 3D (the cell, its 2*dim
-//    neighbours, the cells two steps away and the diagonals) -- and re-tests
-//    the cell and its neighbours from those registers;
-//  * the enabling test compares times strictly; only when a candidate's time
-//    equals a neighbour's (rare in binary64) does the wavefront take the path
-//    that resolves the tie by global index;
-//  * the newly enabled cells of a wavefront are appended with one LDS atomic.
+// Used for tiles that span no lattice direction (the region visit itself is
+// in aca_region.h).  Block b visits tile b; the last block to finish
+// publishes the launch's counters to pinned host memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "aca_device.h"
 #include "aca_internal.h"
-
-#pragma clang fp contract(off)
+#include "aca_region.h"
 
 namespace aca {
 namespace {
-
-constexpr uint64_t kSign = 0x8000000000000000ull;
-constexpr uint64_t kMask = 0x7FFFFFFFFFFFFFFFull;
-
-__device__ __forceinline__ uint64_t ldw(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ void stw(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Pending time of a packed word: the spin is the sign bit and every time is
-// positive, so |word as binary64| is the time (a free source modifier), and
-// binary64 order on these values is the order of their bit patterns.
-__device__ __forceinline__ double time_of(uint64_t w)
-{
-    return __builtin_fabs(__longlong_as_double((long long)w));
-}
-
-__device__ __forceinline__ int wrap_into(int g, int side)
-{
-    g = (g < 0) ? g + side : g;
-    return (g >= side) ? g - side : g;
-}
-
-// Stencil of offsets loaded after an arrival: index 0 the cell, 1..2D the
-// unit steps in slot order (+x, -x, +y, -y, +z, -z), then the steps of two
-// along each axis, then the diagonals (two axes, one step each).
-template <int DIM>
-struct Stencil {
-    static constexpr int Z = 2 * DIM;
-    static constexpr int K = 1 + 4 * DIM + 2 * DIM * (DIM - 1);
-    int d[K][3];
-    int nb[Z + 1][Z];   // nb[s][j]: stencil index of (candidate s) + (unit step j)
-
-    constexpr Stencil() : d(), nb()
-    {
-        int k = 1;
-        for (int a = 0; a < DIM; ++a)
-            for (int s = 1; s >= -1; s -= 2) {
-                d[k][0] = d[k][1] = d[k][2] = 0;
-                d[k][a] = s;
-                ++k;
-            }
-        for (int a = 0; a < DIM; ++a)
-            for (int s = 2; s >= -2; s -= 4) {
-                d[k][0] = d[k][1] = d[k][2] = 0;
-                d[k][a] = s;
-                ++k;
-            }
-        for (int a = 0; a < DIM; ++a)
-            for (int b = a + 1; b < DIM; ++b)
-                for (int sa = 1; sa >= -1; sa -= 2)
-                    for (int sb = 1; sb >= -1; sb -= 2) {
-                        d[k][0] = d[k][1] = d[k][2] = 0;
-                        d[k][a] = sa;
-                        d[k][b] = sb;
-                        ++k;
-                    }
-        for (int s = 0; s <= Z; ++s)
-            for (int j = 0; j < Z; ++j) {
-                const int want[3] = {d[s][0] + d[1 + j][0], d[s][1] + d[1 + j][1],
-                                     d[s][2] + d[1 + j][2]};
-                nb[s][j] = -1;
-                for (int q = 0; q < K; ++q)
-                    if (d[q][0] == want[0] && d[q][1] == want[1] && d[q][2] == want[2])
-                        nb[s][j] = q;
-            }
-    }
-};
-
-struct FastPlan {
-    size_t thr_off, ctr_off, tab_off, ts_off, n_off, f_off, claim_off, list_off, list_cap,
-        total;
-};
-
-// Pitched box: pitch[d] = the largest region box side along d in this launch.
-__host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim)
-{
-    int pitch[3] = {1, 1, 1}, inner = 1;
-    for (int d = 0; d < dim; ++d) {
-        pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2;
-        inner *= a.tile[d] + 2 * a.ghost[d];
-    }
-    const size_t boxp = (size_t)pitch[0] * pitch[1] * pitch[2];
-    FastPlan p;
-    p.thr_off = 0;                                              // uint64 thr[16]
-    p.ctr_off = 128;                                            // int ctr[16]
-    p.tab_off = 192;                                            // uint32 tx, ty, tz
-    // uint64 ts[boxp] with a guard of 2*pitch[0] words on both sides: the
-    // stencil's two-step loads around a cell on the first or last simulated
-    // layer may reach one layer beyond the box (those values are never used)
-    const size_t guard = 2 * (size_t)pitch[0];
-    p.ts_off = (p.tab_off + 4 * (size_t)(pitch[0] + pitch[1] + pitch[2]) + 7) & ~(size_t)7;
-    p.ts_off += 8 * guard;
-    p.n_off = p.ts_off + 8 * (boxp + guard);                    // uint32 n[boxp]
-    p.f_off = p.n_off + 4 * boxp;                               // uint16 f[boxp]
-    p.claim_off = (p.f_off + 2 * boxp + 3) & ~(size_t)3;        // uint32 bits
-    p.list_off = p.claim_off + 4 * ((boxp + 31) / 32);
-    p.list_cap = (size_t)inner / 2 + 2;                         // uint16 list[2][cap]
-    p.total = (p.list_off + 4 * p.list_cap + 15) & ~(size_t)15;
-    return p;
-}
 
 template <int DIM>
 __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int Z = 2 * DIM;
-    constexpr Stencil<DIM> S{};
-    constexpr int K = Stencil<DIM>::K;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int nthreads = blockDim.x;
-
     const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                                       (unsigned)a.ntiles[2];
-    // a tile whose owned cells are final in both snapshots has nothing to do
-    if (a.dead[blockIdx.x]) {
-        if (threadIdx.x == 0) finish_visit_block(a, ntiles_total);
-        return;
-    }
-    // ---- geometry: box coordinates 0..rin+1 (ring at both ends) per axis
-    int tc[3];
-    {
-        uint32_t b = blockIdx.x;
-        tc[0] = (int)(b % (uint32_t)a.ntiles[0]);
-        b /= (uint32_t)a.ntiles[0];
-        tc[1] = (int)(b % (uint32_t)a.ntiles[1]);
-        tc[2] = (int)(b / (uint32_t)a.ntiles[1]);
-    }
-    int rin[3], org[3], olo[3], ohi[3], side[3], pitch[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d < DIM) {
-            side[d] = a.L[d];
-            const int lo = tc[d] * a.tile[d];
-            const int w = min(a.tile[d], a.L[d] - lo);
-            rin[d] = w + 2 * a.ghost[d];
-            org[d] = lo - a.ghost[d] - 1;                 // global coordinate of box 0
-            olo[d] = a.ghost[d] + 1;                      // own cells, box coordinates
-            ohi[d] = a.ghost[d] + 1 + w;
-            pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2;
-        } else {
-            side[d] = 1; rin[d] = 1; org[d] = 0; olo[d] = 0; ohi[d] = 1; pitch[d] = 1;
+    const region::Snapshots io{a.key_in, a.time_in, a.key_out, a.time_out};
+    const region::RegionTally r = region::visit_region<DIM>(a, io, blockIdx.x, lds);
+    if (threadIdx.x == 0) {
+        if (!r.skipped) {
+            unsigned long long *gc = a.counters;
+            atomicAdd(&gc[kEvents], (unsigned long long)r.events);
+            atomicAdd(&gc[kFlips], (unsigned long long)r.flips);
+            atomicAdd(&gc[kGhostEvents], (unsigned long long)r.ghost);
+            atomicAdd(&gc[kChecks], (unsigned long long)r.checks);
+            atomicAdd(&gc[kSweeps], (unsigned long long)r.rounds);
+            if (r.any_live) atomicAdd(&gc[kLiveTiles], 1ull);
+            // owned cells that were all at or past the horizon when loaded can
+            // never change again: both snapshots now hold them
+            if (!r.own_due) a.dead[blockIdx.x] = 1;
         }
-    }
-    const int P1 = pitch[0], P12 = pitch[0] * pitch[1];
-    const int rb[3] = {DIM > 0 ? rin[0] + 2 : 1, DIM > 1 ? rin[1] + 2 : 1, DIM > 2 ? rin[2] + 2 : 1};
-    const int inner = rin[0] * rin[1] * rin[2];
-    const uint32_t magic1 = 0xFFFFFFFFu / (uint32_t)P1 + 1u;            // P1 >= 3
-    const uint32_t magic2 = pitch[1] > 1 ? 0xFFFFFFFFu / (uint32_t)pitch[1] + 1u : 0u;
-
-    const FastPlan plan = fast_plan(a, DIM);
-    uint64_t *thr = reinterpret_cast<uint64_t *>(lds + plan.thr_off);
-    int *ctr = reinterpret_cast<int *>(lds + plan.ctr_off);
-    uint32_t *tx = reinterpret_cast<uint32_t *>(lds + plan.tab_off);
-    uint32_t *ty = tx + pitch[0];
-    uint32_t *tz = ty + pitch[1];
-    uint64_t *ts = reinterpret_cast<uint64_t *>(lds + plan.ts_off);
-    uint32_t *nl = reinterpret_cast<uint32_t *>(lds + plan.n_off);
-    uint16_t *fl = reinterpret_cast<uint16_t *>(lds + plan.f_off);
-    uint32_t *claim = reinterpret_cast<uint32_t *>(lds + plan.claim_off);
-    uint16_t *lists = reinterpret_cast<uint16_t *>(lds + plan.list_off);
-    const int cap = (int)plan.list_cap;
-    int *sizes = ctr;        // [0..2] list lengths, rotating over rounds
-    int *takes = ctr + 3;    // [3..5] take positions, rotating over rounds
-
-    // ---- tables: global offsets of box rows/columns/planes; clear claims
-    if (tid < 2 * (Z + 1)) thr[tid] = a.thr[tid];
-    if (tid < 16) ctr[tid] = 0;
-    for (int j = tid; j < rb[0]; j += nthreads) tx[j] = (uint32_t)wrap_into(org[0] + j, side[0]);
-    for (int j = tid; j < rb[1]; j += nthreads)
-        ty[j] = (uint32_t)(DIM > 1 ? wrap_into(org[1] + j, side[1]) : 0) * (uint32_t)side[0];
-    for (int j = tid; j < rb[2]; j += nthreads)
-        tz[j] = (uint32_t)(DIM > 2 ? wrap_into(org[2] + j, side[2]) : 0) * (uint32_t)side[0] *
-                (uint32_t)side[1];
-    const int boxp = pitch[0] * pitch[1] * pitch[2];
-    for (int j = tid; j < (boxp + 31) / 32; j += nthreads) claim[j] = 0u;
-    __syncthreads();
-
-    // ---- load the region box from the snapshot; note whether any owned
-    // cell still has an arrival before the horizon
-    bool due = false;
-    const int nbox = rb[0] * rb[1] * rb[2];
-    for (int j = tid; j < nbox; j += nthreads) {
-        const int q0 = j % rb[0];
-        const int r = j / rb[0];
-        const int q1 = r % rb[1];
-        const int q2 = r / rb[1];
-        const int bi = q0 + P1 * q1 + P12 * q2;
-        const uint32_t gi = tx[q0] + ty[q1] + tz[q2];
-        const unsigned long long key = a.key_in[gi];
-        const unsigned long long tb = a.time_in[gi];
-        ts[bi] = (uint64_t)tb | ((key & 1ull) << 63);
-        const bool in0 = q0 >= 1 && q0 <= rin[0];
-        const bool in1 = DIM < 2 || (q1 >= 1 && q1 <= rin[1]);
-        const bool in2 = DIM < 3 || (q2 >= 1 && q2 <= rin[2]);
-        if (in0 && in1 && in2) {
-            nl[bi] = (uint32_t)(key >> 32);
-            fl[bi] = 0;
-            const bool own = q0 >= olo[0] && q0 < ohi[0] &&
-                             (DIM < 2 || (q1 >= olo[1] && q1 < ohi[1])) &&
-                             (DIM < 3 || (q2 >= olo[2] && q2 < ohi[2]));
-            due = due || (own && (uint64_t)tb < a.horizon_bits);
-        }
-    }
-    const int own_due = __syncthreads_or(due ? 1 : 0);
-
-    const uint64_t horizon = a.horizon_bits;
-    const double horizon_t = __longlong_as_double((long long)a.horizon_bits);
-    const bool unit_rate = a.unit_rate != 0;
-    uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
-
-    // Box offset of stencil entry k.
-    auto off = [&](int k) { return S.d[k][0] + P1 * S.d[k][1] + P12 * S.d[k][2]; };
-
-    // Exact enabling test (index tie rule) for the cell at box coordinates q
-    // with time tc, given its neighbour times tn[j] in slot order.
-    auto exact = [&](uint64_t tc, const uint64_t *tn, const int *q) {
-        bool en = tc < horizon;
-#pragma unroll
-        for (int j = 0; j < Z; ++j) {
-            const int ax = j >> 1;
-            const uint32_t g = ax == 0 ? tx[q[0]] : (ax == 1 ? ty[q[1]] : tz[q[2]]);
-            const uint32_t unit = ax == 0 ? 1u
-                                  : (ax == 1 ? (uint32_t)side[0]
-                                             : (uint32_t)side[0] * (uint32_t)side[1]);
-            // +axis neighbour has the larger global index unless it wraps;
-            // -axis neighbour the smaller one unless it wraps
-            const bool wins = (j & 1) ? (g == 0u) : (g != (uint32_t)(side[ax] - 1) * unit);
-            en = en && (tc < tn[j] || (tc == tn[j] && wins));
-        }
-        return en;
-    };
-
-    int rounds = 0;
-    if (own_due) {
-    // ---- initial scan: every enabled simulated cell, claimed, into list 0
-    for (int base = tid - lane; base < inner; base += nthreads) {
-        const int i = base + lane;
-        bool en = false;
-        int bi = 0;
-        if (i < inner) {
-            int q[3];
-            q[0] = i % rin[0] + 1;
-            const int r = i / rin[0];
-            q[1] = (DIM > 1) ? r % rin[1] + 1 : 0;
-            q[2] = (DIM > 2) ? r / rin[1] + 1 : 0;
-            bi = q[0] + P1 * q[1] + P12 * q[2];
-            const uint64_t wc = ldw(&ts[bi]);
-            uint64_t tn[Z];
-            double tmin = time_of(ldw(&ts[bi + off(1)]));
-            tn[0] = 0;
-#pragma unroll
-            for (int j = 0; j < Z; ++j) {
-                tn[j] = ldw(&ts[bi + off(1 + j)]);
-                if (j) tmin = __builtin_fmin(tmin, time_of(tn[j]));
-            }
-            const double tc = time_of(wc);
-            const bool due = tc < horizon_t;
-            en = due && tc < tmin;
-            if (due && tc == tmin) {
-#pragma unroll
-                for (int j = 0; j < Z; ++j) tn[j] &= kMask;
-                en = exact(wc & kMask, tn, q);
-            }
-            ++my_checks;
-            if (en) atomicOr(&claim[bi >> 5], 1u << (bi & 31));
-        }
-        const uint64_t m = __ballot(en);
-        if (m) {
-            int b0 = 0;
-            if (lane == 0) b0 = atomicAdd(&sizes[0], (int)__popcll(m));
-            b0 = __shfl(b0, 0, 64);
-            if (en) lists[b0 + (int)__popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)bi;
-        }
-    }
-    __syncthreads();
-
-    // ---- worklist rounds
-    for (int rnd = 0; rnd < a.max_sweeps; ++rnd) {
-        const int sz = sizes[rnd % 3];
-        if (sz == 0) break;
-        ++rounds;
-        if (tid == 0) {
-            sizes[(rnd + 2) % 3] = 0;
-            takes[(rnd + 2) % 3] = 0;
-        }
-        const uint16_t *lcur = lists + (rnd & 1) * cap;
-        uint16_t *lnext = lists + (1 - (rnd & 1)) * cap;
-        int *next_size = &sizes[(rnd + 1) % 3];
-        for (;;) {
-            int start = 0;
-            if (lane == 0) start = atomicAdd(&takes[rnd % 3], 64);
-            start = __shfl(start, 0, 64);
-            if (start >= sz) break;
-            const bool active = lane < sz - start;
-            int bi = 0, q[3] = {0, 0, 0};
-            uint64_t W[K];
-            if (active) {
-                bi = lcur[start + lane];
-                const int row = (int)__umulhi((uint32_t)bi, magic1);   // q1 + pitch1 q2
-                q[0] = bi - row * P1;
-                if (DIM > 2) {
-                    q[2] = (int)__umulhi((uint32_t)row, magic2);
-                    q[1] = row - q[2] * pitch[1];
-                } else {
-                    q[1] = row;
-                }
-                atomicAnd(&claim[bi >> 5], ~(1u << (bi & 31)));
-                // the cell and its neighbour slots: stable until it applies
-                // its arrival (no neighbour can be enabled meanwhile)
-#pragma unroll
-                for (int k = 0; k <= Z; ++k) W[k] = ldw(&ts[bi + off(k)]);
-                int sum = 0;
-#pragma unroll
-                for (int j = 1; j <= Z; ++j) sum += (W[j] >> 63) ? -1 : 1;
-                const uint32_t kn = nl[bi];
-                const uint32_t gidx = tx[q[0]] + ty[q[1]] + tz[q[2]];
-                const Draw y = philox4x32_10(kn, gidx, 0u, 0u, a.key_lo, a.key_hi);
-                const int idx = (sum + Z) / 2 + (Z + 1) * ((W[0] >> 63) ? 0 : 1);
-                const bool flip = (uint64_t)y.w2 < thr[idx];
-                const double tnow = __longlong_as_double((long long)(W[0] & kMask));
-                const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
-                const uint64_t wnew = (uint64_t)__double_as_longlong(tnext) |
-                                      ((W[0] & kSign) ^ (flip ? kSign : 0ull));
-                nl[bi] = kn + 1u;
-                fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                stw(&ts[bi], wnew);
-                W[0] = wnew;
-                bool own = true;
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) own = own && q[d] >= olo[d] && q[d] < ohi[d];
-                if (own) {
-                    ++my_events;
-                    my_flips += flip ? 1u : 0u;
-                } else {
-                    ++my_ghost;
-                }
-            }
-            // The rest of the neighbourhood is read only after this lane's
-            // arrival is published: of two cells that share a neighbour and
-            // apply arrivals concurrently, the one that reads later then sees
-            // both new words, so a neighbour they both unblocked is found.
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-            if (active) {
-#pragma unroll
-                for (int k = Z + 1; k < K; ++k) {
-                    int at = bi + off(k);
-                    // two steps along z may leave the box (and its guard);
-                    // such words are never used, so any in-range address will do
-                    if (DIM > 2 && (S.d[k][2] == 2 || S.d[k][2] == -2))
-                        at = min(max(at, 0), boxp - 1);
-                    W[k] = ldw(&ts[at]);
-                }
-            }
-            // re-test the applied cell (s = 0) and its neighbours (s = 1..Z):
-            // enabled when its time is below the horizon and below the least
-            // neighbour time; equal to it only on a tie of binary64 times
-            bool want[Z + 1];
-            bool tie[Z + 1];
-            bool any_tie = false;
-#pragma unroll
-            for (int s = 0; s <= Z; ++s) {
-                bool inside = active;
-                if (s > 0) {
-                    const int ax = (s - 1) >> 1;
-                    const int qs = q[ax] + (((s - 1) & 1) ? -1 : 1);
-                    inside = inside && qs >= 1 && qs <= rin[ax];
-                }
-                const double tc = time_of(W[s]);
-                double tmin = time_of(W[S.nb[s][0]]);
-#pragma unroll
-                for (int j = 1; j < Z; ++j) tmin = __builtin_fmin(tmin, time_of(W[S.nb[s][j]]));
-                const bool live = inside && tc < horizon_t;
-                want[s] = live && tc < tmin;
-                tie[s] = live && tc == tmin;
-                any_tie = any_tie || tie[s];
-                my_checks += inside ? 1u : 0u;
-            }
-            if (__ballot(any_tie)) {
-#pragma unroll
-                for (int s = 0; s <= Z; ++s) {
-                    if (tie[s]) {
-                        int qs[3] = {q[0], q[1], q[2]};
-                        if (s > 0) qs[(s - 1) >> 1] += ((s - 1) & 1) ? -1 : 1;
-                        uint64_t tn[Z];
-#pragma unroll
-                        for (int j = 0; j < Z; ++j) tn[j] = W[S.nb[s][j]] & kMask;
-                        want[s] = exact(W[s] & kMask, tn, qs);
-                    }
-                }
-            }
-            // claim; a cell already claimed by another lane is not listed twice
-            int cb[Z + 1];
-#pragma unroll
-            for (int s = 0; s <= Z; ++s) {
-                cb[s] = bi + off(s);
-                if (want[s]) {
-                    const uint32_t bit = 1u << (cb[s] & 31);
-                    want[s] = (atomicOr(&claim[cb[s] >> 5], bit) & bit) == 0u;
-                }
-            }
-            // one LDS atomic per wavefront for all its new list entries
-            uint64_t mk[Z + 1];
-            int total = 0;
-#pragma unroll
-            for (int s = 0; s <= Z; ++s) {
-                mk[s] = __ballot(want[s]);
-                total += (int)__popcll(mk[s]);
-            }
-            if (total) {
-                int b0 = 0;
-                if (lane == 0) b0 = atomicAdd(next_size, total);
-                b0 = __shfl(b0, 0, 64);
-                const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-                for (int s = 0; s <= Z; ++s) {
-                    if (want[s]) lnext[b0 + (int)__popcll(mk[s] & below)] = (uint16_t)cb[s];
-                    b0 += (int)__popcll(mk[s]);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    }  // own_due
-
-    // ---- merge owned copies and moved ghost copies; find due owned cells
-    bool live = false;
-    for (int j = tid; j < inner; j += nthreads) {
-        int q[3];
-        q[0] = j % rin[0] + 1;
-        const int r = j / rin[0];
-        q[1] = (DIM > 1) ? r % rin[1] + 1 : 0;
-        q[2] = (DIM > 2) ? r / rin[1] + 1 : 0;
-        const int bi = q[0] + P1 * q[1] + P12 * q[2];
-        bool own = true;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) own = own && q[d] >= olo[d] && q[d] < ohi[d];
-        const uint32_t gi = tx[q[0]] + ty[q[1]] + tz[q[2]];
-        const uint32_t n_copy = nl[bi];
-        const unsigned long long key_in = a.key_in[gi];
-        const uint64_t wd = ts[bi];
-        if (own || n_copy != (uint32_t)(key_in >> 32)) {
-            const unsigned long long f = ((key_in >> 1) & 0x7FFFFFFFull) + fl[bi];
-            atomicMax(&a.key_out[gi], ((unsigned long long)n_copy << 32) | (f << 1) | (wd >> 63));
-            atomicMax(&a.time_out[gi], (unsigned long long)(wd & kMask));
-        }
-        if (own) live = live || (wd & kMask) < horizon;
-    }
-    atomicAdd(&ctr[6], (int)my_events);
-    atomicAdd(&ctr[7], (int)my_flips);
-    atomicAdd(&ctr[8], (int)my_ghost);
-    atomicAdd(&ctr[9], (int)my_checks);
-    const int any_live = __syncthreads_or(live ? 1 : 0);
-    if (tid == 0) {
-        unsigned long long *gc = a.counters;
-        atomicAdd(&gc[kEvents], (unsigned long long)(unsigned)ctr[6]);
-        atomicAdd(&gc[kFlips], (unsigned long long)(unsigned)ctr[7]);
-        atomicAdd(&gc[kGhostEvents], (unsigned long long)(unsigned)ctr[8]);
-        atomicAdd(&gc[kChecks], (unsigned long long)(unsigned)ctr[9]);
-        atomicAdd(&gc[kSweeps], (unsigned long long)rounds);
-        if (any_live) atomicAdd(&gc[kLiveTiles], 1ull);
-        // owned cells that were all at or past the horizon when loaded can
-        // never change again: both snapshots now hold them
-        if (!own_due) a.dead[blockIdx.x] = 1;
         finish_visit_block(a, ntiles_total);
     }
 }
 
 }  // namespace
 
-size_t visit_fast_lds_bytes(int dim, const VisitArgs &a) { return fast_plan(a, dim).total; }
+size_t visit_fast_lds_bytes(int dim, const VisitArgs &a) { return region::fast_plan(a, dim).total; }
 
 int visit_fast_box(int dim, const VisitArgs &a)
 {

@@ -106,3 +106,28 @@ def test_null_arguments_rejected():
     # scratch too small
     assert lib.aca_create(ctypes.byref(p), 256, 512, 768, 1024, 16,
                           ctypes.byref(h)) == aca.ACA_ENOMEM
+
+
+def test_batch_query_and_argument_checks():
+    lib = aca.load()
+    nb = ctypes.c_uint64()
+    assert lib.aca_batch_query(512, ctypes.byref(nb)) == aca.ACA_OK
+    small = nb.value
+    assert lib.aca_batch_query(4096, ctypes.byref(nb)) == aca.ACA_OK
+    assert nb.value > small > 512 * 100
+    assert lib.aca_batch_query(0, ctypes.byref(nb)) == aca.ACA_EINVAL
+    assert lib.aca_batch_query(1 << 21, ctypes.byref(nb)) == aca.ACA_EINVAL
+    assert lib.aca_batch_query(8, None) == aca.ACA_EINVAL
+    h = ctypes.c_void_p()
+    # NULL / misaligned / too small work buffers are refused before device work
+    assert lib.aca_batch_create(8, None, 1 << 20, ctypes.byref(h)) == aca.ACA_EINVAL
+    assert lib.aca_batch_create(8, 8, 1 << 20, ctypes.byref(h)) == aca.ACA_EINVAL
+    assert lib.aca_batch_create(8, 256, 16, ctypes.byref(h)) == aca.ACA_ENOMEM
+    assert lib.aca_batch_create(0, 256, 1 << 20, ctypes.byref(h)) == aca.ACA_EINVAL
+    assert lib.aca_batch_step(None, 0.0, 0, None, None) == aca.ACA_EINVAL
+    assert lib.aca_batch_attach(None, None, 1.0) == aca.ACA_EINVAL
+    n = ctypes.c_int32()
+    assert lib.aca_batch_poll(None, None, 0, ctypes.byref(n)) == aca.ACA_EINVAL
+    assert lib.aca_batch_members(None, None, 0, ctypes.byref(n)) == aca.ACA_EINVAL
+    assert lib.aca_batch_set_tuning(None, 2, None) == aca.ACA_EINVAL
+    assert lib.aca_batch_destroy(None) == aca.ACA_OK
