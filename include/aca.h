@@ -267,6 +267,91 @@ aca_status aca_batch_get_stats(const aca_batch *b, aca_batch_stats *out);
 /* Release the handle; ACA_ESTATE while it has members. */
 aca_status aca_batch_destroy(aca_batch *b);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A server runs simulation jobs that arrive over time (continuous batching):
+ * aca_server_submit queues a job; every aca_server_step first admits queued
+ * jobs in arrival order while a batch slot and room in the device arena are
+ * free (the job's state buffers and scratch are carved from the arena and
+ * its initial state is drawn on the device), then runs one batch step with a
+ * device-time budget, so jobs that arrive while others run join at the next
+ * step and share the GPU with them.  A finished job's state stays in the
+ * arena until aca_server_release.  Results are bit-identical to running the
+ * job alone with aca_init + aca_advance.  One server is driven from one host
+ * thread.
+ */
+typedef struct aca_server aca_server;   /* opaque host handle */
+
+enum { ACA_JOB_QUEUED = 0, ACA_JOB_RUNNING = 1, ACA_JOB_DONE = 2, ACA_JOB_FAILED = 3 };
+
+typedef struct aca_server_stats {
+    uint32_t struct_size;
+    uint32_t pad_;
+    uint64_t submitted;      /* jobs accepted by aca_server_submit */
+    uint64_t admitted;       /* jobs given arena memory and a batch slot */
+    uint64_t finished;       /* jobs that reached their horizon */
+    uint64_t failed;         /* jobs that ended with an error */
+    uint64_t steps;          /* aca_server_step calls that ran the batch */
+    uint64_t events;         /* arrivals applied, exact, over finished jobs */
+    uint64_t arena_bytes;    /* size of the arena */
+    uint64_t arena_peak;     /* most arena bytes in use at once */
+    uint64_t queued_peak;    /* most jobs waiting for admission at once */
+    double device_ms;        /* wall time inside aca_server_step (ms) */
+    double kernel_ms;        /* persistent visit-kernel time (ms) */
+} aca_server_stats;
+
+/* Device bytes of the server's work buffer for up to max_jobs jobs at once. */
+aca_status aca_server_query(int32_t max_jobs, uint64_t *work_bytes);
+
+/* Arena bytes one job with parameters p occupies while admitted: its state
+ * buffers (13 bytes per cell) and scratch, each 256-byte aligned. */
+aca_status aca_server_job_bytes(const aca_params *p, uint64_t *bytes);
+
+/* Create a server over two caller-owned, 256-byte aligned device buffers: the
+ * arena that admitted jobs are carved from (its size is the HBM budget) and a
+ * work buffer of work_bytes >= aca_server_query(max_jobs). */
+aca_status aca_server_create(void *d_arena, uint64_t arena_bytes, void *d_work,
+                             uint64_t work_bytes, int32_t max_jobs, aca_server **out);
+
+/* Per-dimension schedule knobs for jobs admitted from now on (as
+ * aca_batch_set_tuning). */
+aca_status aca_server_set_tuning(aca_server *srv, int32_t dim, const aca_tuning *t);
+
+/* Queue a job: lattice p from its initial state to horizon T (finite, > 0).
+ * *job receives its id (ids count up from 0).  ACA_ENOMEM if the job alone
+ * exceeds the arena. */
+aca_status aca_server_submit(aca_server *srv, const aca_params *p, double T, uint64_t *job);
+
+/* Admit what fits, then one batch step of at most budget_ms of device time
+ * (<= 0: until every running job is done).  Writes the ids of jobs that
+ * finished during this call to done[0..cap) (*n_done receives how many
+ * finished; ids beyond cap are still marked done).  Synchronous.  A job whose
+ * batch step failed is marked ACA_JOB_FAILED and its memory released; the
+ * call then returns that error after finishing the step for the others. */
+aca_status aca_server_step(aca_server *srv, double budget_ms, void *stream, uint64_t *done,
+                           int32_t cap, int32_t *n_done);
+
+/* State of a job (ACA_JOB_*), and for finished jobs its statistics. */
+aca_status aca_server_job(const aca_server *srv, uint64_t job, int32_t *state,
+                          aca_stats *stats);
+
+/* Synchronous copy of a finished job's spins, times and counts to host memory
+ * (any pointer may be NULL).  ACA_ESTATE unless the job is done. */
+aca_status aca_server_read(aca_server *srv, uint64_t job, int8_t *h_spin, double *h_time,
+                           uint32_t *h_count, void *stream);
+
+/* Return a finished or failed job's arena memory and forget the job. */
+aca_status aca_server_release(aca_server *srv, uint64_t job);
+
+/* Jobs waiting for admission and jobs running. */
+aca_status aca_server_load(const aca_server *srv, int32_t *queued, int32_t *running);
+
+aca_status aca_server_get_stats(const aca_server *srv, aca_server_stats *out);
+
+/* Release the handle; ACA_ESTATE while jobs are queued or running (finished
+ * jobs not yet released are dropped). */
+aca_status aca_server_destroy(aca_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

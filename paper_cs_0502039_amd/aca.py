@@ -25,7 +25,11 @@ EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_neg_log", "aca_batch_query", "aca_batch_create", "aca_batch_set_tuning",
             "aca_batch_get_tuning", "aca_batch_attach", "aca_batch_step", "aca_batch_poll",
             "aca_batch_advance", "aca_batch_members", "aca_batch_get_stats",
-            "aca_batch_destroy")
+            "aca_batch_destroy", "aca_server_query", "aca_server_job_bytes",
+            "aca_server_create", "aca_server_set_tuning", "aca_server_submit",
+            "aca_server_step", "aca_server_job", "aca_server_read", "aca_server_release",
+            "aca_server_load", "aca_server_get_stats", "aca_server_destroy")
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
 class AcaError(RuntimeError):
@@ -66,6 +70,16 @@ class BatchStats(ctypes.Structure):
                 ("ghost_events", ctypes.c_uint64), ("cell_checks", ctypes.c_uint64),
                 ("finished", ctypes.c_uint64), ("device_ms", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("region_bytes", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("finished", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("events", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
+                ("queued_peak", ctypes.c_uint64), ("device_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double)]
 
 
 _LIB = None
@@ -111,6 +125,18 @@ def load() -> ctypes.CDLL:
         "aca_batch_members": [P, P, i32, P],
         "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
         "aca_batch_destroy": [P],
+        "aca_server_query": [i32, P],
+        "aca_server_job_bytes": [pp, P],
+        "aca_server_create": [P, u64, P, u64, i32, P],
+        "aca_server_set_tuning": [P, i32, pt],
+        "aca_server_submit": [P, pp, f64, P],
+        "aca_server_step": [P, f64, P, P, i32, P],
+        "aca_server_job": [P, u64, P, ps],
+        "aca_server_read": [P, u64, P, P, P, P],
+        "aca_server_release": [P, u64],
+        "aca_server_load": [P, P, P],
+        "aca_server_get_stats": [P, ctypes.POINTER(ServerStats)],
+        "aca_server_destroy": [P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -345,6 +371,105 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None):
             _check(self.lib.aca_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_bytes(p: dict) -> int:
+    """Arena bytes a served job with parameters p occupies."""
+    out = ctypes.c_uint64(0)
+    _check(load().aca_server_job_bytes(ctypes.byref(make_params(p)), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Server:
+    """Continuous batching of simulation jobs over a device arena (HBM budget)."""
+
+    def __init__(self, arena_bytes: int, max_jobs: int = 256, device: str = "cuda",
+                 stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.max_jobs = int(max_jobs)
+        wb = ctypes.c_uint64(0)
+        _check(self.lib.aca_server_query(self.max_jobs, ctypes.byref(wb)))
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.work = torch.empty(int(wb.value), dtype=torch.uint8, device=device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib.aca_server_create(self.arena.data_ptr(), int(arena_bytes),
+                                          self.work.data_ptr(), int(wb.value), self.max_jobs,
+                                          ctypes.byref(h)))
+        self._h = h
+        self._done = (ctypes.c_uint64 * self.max_jobs)()
+        self._n = {}
+
+    def _s(self) -> int:
+        return _stream_ptr(self._torch, self.stream)
+
+    def set_tuning(self, dim: int, **kw) -> None:
+        t = make_tuning(**kw) if kw else None
+        _check(self.lib.aca_server_set_tuning(self._h, int(dim),
+                                              ctypes.byref(t) if t is not None else None))
+
+    def submit(self, params: dict, T: Optional[float] = None) -> int:
+        job = ctypes.c_uint64(0)
+        _check(self.lib.aca_server_submit(self._h, ctypes.byref(make_params(params)),
+                                          float(params["T"] if T is None else T),
+                                          ctypes.byref(job)))
+        self._n[job.value] = query(params)[0]
+        return int(job.value)
+
+    def step(self, budget_ms: float = 0.0) -> list:
+        """Admit what fits, run one batch step; returns ids of jobs that finished."""
+        n = ctypes.c_int32(0)
+        _check(self.lib.aca_server_step(self._h, float(budget_ms), self._s(), self._done,
+                                        self.max_jobs, ctypes.byref(n)))
+        return [int(self._done[i]) for i in range(min(n.value, self.max_jobs))]
+
+    def job(self, job: int) -> tuple[int, dict]:
+        state = ctypes.c_int32(0)
+        st = Stats()
+        st.struct_size = ctypes.sizeof(Stats)
+        _check(self.lib.aca_server_job(self._h, int(job), ctypes.byref(state),
+                                       ctypes.byref(st)))
+        return int(state.value), {k: getattr(st, k) for k, _ in Stats._fields_
+                                  if k not in ("struct_size", "pad_")}
+
+    def read(self, job: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+        n = self._n[job]
+        s = np.empty(n, dtype=np.int8)
+        t = np.empty(n, dtype=np.float64)
+        c = np.empty(n, dtype=np.uint32)
+        _check(self.lib.aca_server_read(self._h, int(job), s.ctypes.data, t.ctypes.data,
+                                        c.ctypes.data, self._s()))
+        return s, t, c
+
+    def release(self, job: int) -> None:
+        _check(self.lib.aca_server_release(self._h, int(job)))
+        self._n.pop(job, None)
+
+    def load(self) -> tuple[int, int]:
+        q = ctypes.c_int32(0)
+        r = ctypes.c_int32(0)
+        _check(self.lib.aca_server_load(self._h, ctypes.byref(q), ctypes.byref(r)))
+        return int(q.value), int(r.value)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        st.struct_size = ctypes.sizeof(ServerStats)
+        _check(self.lib.aca_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_
+                if k not in ("struct_size", "pad_")}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(self.lib.aca_server_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libaca.so")
 SOURCES = ("aca_api.hip", "aca_kernels.hip", "aca_visit_fast.hip", "aca_batch.hip",
-           "aca_batch_api.hip")
+           "aca_batch_api.hip", "aca_server_api.hip")
 ARCH = os.environ.get("ACA_OFFLOAD_ARCH", "gfx950")
 
 

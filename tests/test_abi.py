@@ -131,3 +131,30 @@ def test_batch_query_and_argument_checks():
     assert lib.aca_batch_members(None, None, 0, ctypes.byref(n)) == aca.ACA_EINVAL
     assert lib.aca_batch_set_tuning(None, 2, None) == aca.ACA_EINVAL
     assert lib.aca_batch_destroy(None) == aca.ACA_OK
+
+
+def test_server_host_side_checks():
+    lib = aca.load()
+    nb = ctypes.c_uint64()
+    assert lib.aca_server_query(64, ctypes.byref(nb)) == aca.ACA_OK and nb.value > 0
+    assert lib.aca_server_query(0, ctypes.byref(nb)) == aca.ACA_EINVAL
+    p = workloads.lattice(2, (100, 60), 0.3)
+    n, scratch = aca.query(p)
+    jb = aca.job_bytes(p)
+    # state buffers (1 + 8 + 4 bytes per cell) and scratch, each 256-byte aligned
+    assert jb >= 13 * n + scratch
+    assert jb <= 13 * n + scratch + 4 * 256
+    assert jb % 256 == 0
+    bad = dict(p, dim=5)
+    with pytest.raises(aca.AcaError) as e:
+        aca.job_bytes(bad)
+    assert e.value.code == aca.ACA_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.aca_server_create(None, 1 << 20, 256, 1 << 20, 8, ctypes.byref(h)) == aca.ACA_EINVAL
+    assert lib.aca_server_create(8, 1 << 20, 256, 1 << 20, 8, ctypes.byref(h)) == aca.ACA_EINVAL
+    assert lib.aca_server_create(256, 16, 512, 1 << 20, 8, ctypes.byref(h)) == aca.ACA_EINVAL
+    assert lib.aca_server_submit(None, None, 1.0, None) == aca.ACA_EINVAL
+    n_done = ctypes.c_int32()
+    assert lib.aca_server_step(None, 0.0, None, None, 0, ctypes.byref(n_done)) == aca.ACA_EINVAL
+    assert lib.aca_server_release(None, 0) == aca.ACA_EINVAL
+    assert lib.aca_server_destroy(None) == aca.ACA_OK
