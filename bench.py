@@ -11,7 +11,15 @@ Prints one JSON line.  Besides the contract fields it carries
                 per launch over the launch time measured with HIP events on the
                 launching stream (inside the library), against MI355X peaks;
   cpu_baseline  the serial oracle timed on a bounded sample of the same workload
-                on one host core.
+                on one host core;
+  batched       the 512-lattice workload (sides log-uniform in [32, 1024],
+                uneven temperatures and horizons): one batch advance against the
+                plain path of one init + advance per lattice on one stream, in
+                jobs/s, with the speedup;
+  served        the job stream (80% 2D up to 2048^2, 20% 3D up to 128^3, both
+                rules, horizons up to 1000) through the job server: first all
+                jobs at once (capacity in jobs/s), then Poisson arrivals at 0.7
+                of that capacity, with p50/p99 of result-on-host minus arrival.
 """
 from __future__ import annotations
 
@@ -101,6 +109,146 @@ def cpu_baseline(params: dict, T_sample: float) -> dict:
                        f"counted)")}
 
 
+def bench_batched(steps: int, warmup: int, autotune: bool = True) -> dict:
+    """Batched vs plain on the 512-lattice workload.  With autotune the first
+    warm-up pass lets the batch tuner pick the 2D schedule on the workload itself
+    (the tuner advances the real lattices, so that pass still ends exact)."""
+    import torch
+    from paper_cs_0502039_amd import aca, workloads
+    cases = workloads.batch_512()
+    lats = [aca.Lattice(p) for p in cases]
+    T = [p["T"] for p in cases]
+    batch = aca.Batch(len(cases))
+    log(f"batched: {len(cases)} lattices, {sum(l.n for l in lats)} cells")
+
+    def one_batched():
+        for l in lats:
+            l.init()
+        batch.advance(lats, T)
+
+    tune = None
+    if autotune:
+        for l in lats:
+            l.init()
+        tune = batch.tune(lats, T, 2, frac=0.03)
+        batch.advance(lats, T)
+        log(f"batched: autotuned 2D schedule {tune['tuning']} "
+            f"(rates per ms {[round(r) for r in tune['rates_per_ms']]})")
+    for _ in range(warmup):
+        one_batched()
+    torch.cuda.synchronize()
+    k0 = batch.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_batched()
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / steps
+    k1 = batch.stats()
+    events = (k1["events"] - k0["events"]) // steps
+    log(f"batched: {dt_b * 1e3:.1f} ms per pass, kernel "
+        f"{(k1['kernel_ms'] - k0['kernel_ms']) / steps:.1f} ms")
+    bit_exact = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "batch_512.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)["items"]
+        bit_exact = all(
+            g["params"] == p and digest(*l.read()) == (g["sha256_s"], g["sha256_t"],
+                                                       g["sha256_n"])
+            for g, p, l in zip(gold, cases, lats))
+        log(f"batched: bit-exact vs oracle digests: {bit_exact}")
+    # plain path: one init + advance per lattice, one after another
+    small = aca.Lattice(workloads.lattice(2, (64, 64), 0.4, T=2.0))
+    small.init().advance(2.0)
+    small.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for l, t in zip(lats, T):
+        l.init().advance(t)
+    torch.cuda.synchronize()
+    dt_p = time.perf_counter() - t0
+    log(f"plain: {dt_p * 1e3:.1f} ms per pass")
+    tuning_2d = batch.tuning(2)
+    batch.close()
+    for l in lats:
+        l.close()
+    return {"workload": "batch_512", "lattices": len(cases), "events": events,
+            "ms_batched": dt_b * 1e3, "ms_plain": dt_p * 1e3,
+            "jobs_per_s": len(cases) / dt_b, "plain_jobs_per_s": len(cases) / dt_p,
+            "speedup": dt_p / dt_b, "spin_updates_per_s": events / dt_b,
+            "plain_spin_updates_per_s": events / dt_p, "bit_exact": bit_exact,
+            "tuning_2d": tuning_2d, "autotune": tune, "steps": steps}
+
+
+def serve(jobs, arena_bytes: int, max_jobs: int, budget_ms: float, arrivals=None):
+    """Drive the job server; arrivals[i] is job i's arrival in seconds after the
+    start (None: all at once).  Returns (latencies s, wall s, events, stats)."""
+    from paper_cs_0502039_amd import aca
+    server = aca.Server(arena_bytes, max_jobs=max_jobs)
+    n = len(jobs)
+    order = list(range(n)) if arrivals is None else sorted(range(n), key=lambda i: arrivals[i])
+    t_arr = [0.0] * n if arrivals is None else list(arrivals)
+    ids = {}
+    lat = [0.0] * n
+    done = 0
+    nxt = 0
+    t0 = time.perf_counter()
+    while done < n:
+        now = time.perf_counter() - t0
+        while nxt < n and t_arr[order[nxt]] <= now:
+            i = order[nxt]
+            ids[server.submit(jobs[i])] = i
+            nxt += 1
+        q, r = server.load()
+        if q == 0 and r == 0:
+            # idle until the next arrival
+            wait = t_arr[order[nxt]] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.0005))
+            continue
+        for job in server.step(budget_ms):
+            server.read(job)
+            lat[ids[job]] = time.perf_counter() - t0 - t_arr[ids[job]]
+            server.release(job)
+            done += 1
+    wall = time.perf_counter() - t0
+    st = server.stats()
+    server.close()
+    return lat, wall, st
+
+
+def bench_served(arena_gib: float, max_jobs: int, budget_ms: float, count: int) -> dict:
+    import numpy as np
+    from paper_cs_0502039_amd import workloads
+    stream = workloads.served_stream(count=count, rate_jobs_per_s=1.0)
+    jobs = [{k: v for k, v in j.items() if k not in ("t_arrive", "id")} for j in stream]
+    unit_arrivals = [j["t_arrive"] for j in stream]       # Poisson, rate 1 per second
+    arena = int(arena_gib * (1 << 30))
+    log(f"served: {count} jobs, arena {arena_gib} GiB, {max_jobs} slots, "
+        f"step budget {budget_ms} ms")
+    # warm-up: a few jobs through a small server
+    serve(jobs[:4], arena, max_jobs, budget_ms)
+    _, wall_c, st_c = serve(jobs, arena, max_jobs, budget_ms)
+    capacity = count / wall_c
+    rho = 0.7 * capacity
+    log(f"served: capacity {capacity:.1f} jobs/s ({st_c['events'] / wall_c:.3e} "
+        f"spin-updates/s); open loop at {rho:.1f} jobs/s")
+    arrivals = [t / rho for t in unit_arrivals]
+    lat, wall, st = serve(jobs, arena, max_jobs, budget_ms, arrivals)
+    lat_ms = np.array(lat) * 1e3
+    return {"workload": "served_stream", "jobs": count, "arena_gib": arena_gib,
+            "max_jobs": max_jobs, "step_budget_ms": budget_ms,
+            "capacity_jobs_per_s": capacity,
+            "capacity_spin_updates_per_s": st_c["events"] / wall_c,
+            "rho_jobs_per_s": rho, "jobs_per_s": count / wall,
+            "spin_updates_per_s": st["events"] / wall,
+            "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)),
+            "max_ms": float(lat_ms.max()), "mean_ms": float(lat_ms.mean()),
+            "events": st["events"], "steps": st["steps"],
+            "arena_peak_gib": st["arena_peak"] / (1 << 30), "queued_peak": st["queued_peak"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +264,15 @@ def main() -> int:
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 2 GiB device copy (for counter scaling)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the automatic schedules instead of tuning on the workload")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--only", choices=("single", "batched", "served"), default=None)
+    ap.add_argument("--serve-jobs", type=int, default=400)
+    ap.add_argument("--serve-arena-gib", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=512)
+    ap.add_argument("--serve-budget-ms", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the workload is a single "
@@ -126,9 +283,19 @@ def main() -> int:
     import torch
     from paper_cs_0502039_amd import aca, workloads
 
+    torch.cuda.set_device(0)
+    if args.only == "batched":
+        print(json.dumps({"batched": bench_batched(args.steps, args.warmup,
+                                                   not args.no_autotune)}), flush=True)
+        return 0
+    if args.only == "served":
+        print(json.dumps({"served": bench_served(args.serve_arena_gib, args.serve_slots,
+                                                 args.serve_budget_ms, args.serve_jobs)}),
+              flush=True)
+        return 0
+
     params = getattr(workloads, args.workload)()
     T = params["T"]
-    torch.cuda.set_device(0)
     if args.calibrate_copy:
         copy_calibration()
     lat = aca.Lattice(params)
@@ -143,6 +310,15 @@ def main() -> int:
         if args.block:
             kw["block"] = args.block
         lat.set_tuning(**kw)
+    tune = None
+    if not (args.no_autotune or args.tile or args.ghost or args.sweeps or args.block):
+        # the tuner advances the real lattice slice by slice; the warm-up pass
+        # then finishes it (same final state whichever schedule wins)
+        lat.init()
+        tune = lat.tune(max(T / 20.0, 1e-3))
+        lat.advance(T)
+        log(f"autotuned: {tune['tuning']} (rates per ms "
+            f"{[round(r) for r in tune['rates_per_ms']]})")
     log(f"bench: {args.workload} L={params['L']} T={T} tuning={lat.tuning()}")
 
     for i in range(args.warmup):
@@ -193,7 +369,8 @@ def main() -> int:
             log(f"bit-exact vs oracle digest: {bit_exact}")
 
     out = {
-        "metric": "spin-updates/s at 4096^2 (bit-exact)",
+        "metric": "spin-updates/s at 4096^2 (bit-exact); batched vs plain speedup; "
+                  "p99 job latency",
         "value": value,
         "unit": "spin-updates/s",
         "n_gpus": 1,
@@ -208,7 +385,7 @@ def main() -> int:
         "config": {"workload": args.workload, "dim": params["dim"], "L": params["L"],
                    "T": T, "beta": params["beta"], "h": params["h"], "rule": params["rule"],
                    "init": params["init"], "seed": params["seed"],
-                   "tuning": lat.tuning()},
+                   "tuning": lat.tuning(), "autotuned": tune is not None},
         "roofline": roofline,
         "roofline_other": other,
         "bit_exact": bit_exact,
@@ -221,6 +398,12 @@ def main() -> int:
         "ghost_events_per_event": st["ghost_events"] / max(1, events),
     }
     lat.close()
+    del lat
+    if args.only is None and not args.no_batched:
+        out["batched"] = bench_batched(args.steps, args.warmup, not args.no_autotune)
+    if args.only is None and not args.no_served:
+        out["served"] = bench_served(args.serve_arena_gib, args.serve_slots,
+                                     args.serve_budget_ms, args.serve_jobs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, args.cpu_sample_T)
     print(json.dumps(out), flush=True)

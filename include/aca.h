@@ -151,6 +151,21 @@ aca_status aca_advance(aca_lattice *lat, double T, void *stream);
 
 aca_status aca_get_stats(const aca_lattice *lat, aca_stats *out);
 
+/* Autotuning on the caller's own work.  Every schedule yields the same
+ * trajectory (Fig. 3.4's partition invariance), so the tuner advances the
+ * real lattice: first a warm-up slice of dT/2 with the first candidate, then
+ * one slice of dT per candidate, each timed on the device; it keeps the
+ * candidate with the most arrivals per millisecond, installs it with
+ * aca_set_tuning and leaves the lattice advanced by (n + 1/2) dT.  cands NULL
+ * (or n = 0) uses the library's candidate set for the lattice's dimension.
+ * rates (may be NULL) receives arrivals per millisecond of each candidate
+ * (n entries; with cands NULL, up to ACA_TUNE_MAX entries, *n_out their
+ * number). */
+#define ACA_TUNE_MAX 16
+aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_t n, double dT,
+                    void *stream, int32_t *best, double *rates, int32_t *n_out);
+
+
 /* Synchronous copy of the state to host memory (any pointer may be NULL). */
 aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
                     uint32_t *h_count, void *stream);
@@ -230,6 +245,13 @@ aca_status aca_batch_create(int32_t capacity, void *d_work, uint64_t work_bytes,
 aca_status aca_batch_set_tuning(aca_batch *b, int32_t dim, const aca_tuning *t);
 aca_status aca_batch_get_tuning(const aca_batch *b, int32_t dim, aca_tuning *out);
 
+/* Order in which workgroups take open items of the members: ACA_ORDER_WORK
+ * (default) serves the member with the most remaining arrivals first, which
+ * shortens the whole batch; ACA_ORDER_ARRIVAL serves members in the order
+ * they were attached, which bounds each member's wait (job serving). */
+enum { ACA_ORDER_WORK = 0, ACA_ORDER_ARRIVAL = 1 };
+aca_status aca_batch_set_order(aca_batch *b, int32_t order);
+
 /* Add an initialised lattice that is not a member of any batch, to be
  * advanced to horizon T (finite, >= its last horizon).  It joins at the next
  * step.  ACA_ENOMEM when the batch is full. */
@@ -256,6 +278,19 @@ aca_status aca_batch_poll(aca_batch *b, aca_lattice **done, int32_t cap,
  * buffers and the finished queue empty. */
 aca_status aca_batch_advance(aca_batch *b, aca_lattice *const *lats, const double *T,
                              int32_t count, void *stream);
+
+
+/* Batch autotuning for the members of dimension dim (as aca_tune): the batch
+ * must be empty; lats[i] (initialised, horizons T[i]) are advanced slice by
+ * slice, each slice a fraction frac of every lattice's remaining span to
+ * T[i], one candidate per slice after a warm-up slice; the candidate with the
+ * most arrivals per millisecond of device time becomes the batch's tuning for
+ * dim.  Lattices of other dimensions advance too.  The lattices are left
+ * detached, short of their horizons. */
+aca_status aca_batch_tune(aca_batch *b, aca_lattice *const *lats, const double *T,
+                          int32_t count, int32_t dim, const aca_tuning *cands, int32_t n,
+                          double frac, void *stream, int32_t *best, double *rates,
+                          int32_t *n_out);
 
 /* The current members, up to cap of them, in slot order (*n_members gets
  * their total number). */
@@ -316,6 +351,10 @@ aca_status aca_server_create(void *d_arena, uint64_t arena_bytes, void *d_work,
 /* Per-dimension schedule knobs for jobs admitted from now on (as
  * aca_batch_set_tuning). */
 aca_status aca_server_set_tuning(aca_server *srv, int32_t dim, const aca_tuning *t);
+
+/* Priority among running jobs (ACA_ORDER_*; the server starts with
+ * ACA_ORDER_ARRIVAL). */
+aca_status aca_server_set_order(aca_server *srv, int32_t order);
 
 /* Queue a job: lattice p from its initial state to horizon T (finite, > 0).
  * *job receives its id (ids count up from 0).  ACA_ENOMEM if the job alone

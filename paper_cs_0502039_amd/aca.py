@@ -28,7 +28,10 @@ EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_batch_destroy", "aca_server_query", "aca_server_job_bytes",
             "aca_server_create", "aca_server_set_tuning", "aca_server_submit",
             "aca_server_step", "aca_server_job", "aca_server_read", "aca_server_release",
-            "aca_server_load", "aca_server_get_stats", "aca_server_destroy")
+            "aca_server_load", "aca_server_get_stats", "aca_server_destroy", "aca_tune",
+            "aca_batch_tune", "aca_batch_set_order", "aca_server_set_order")
+ORDER_WORK, ORDER_ARRIVAL = 0, 1
+TUNE_MAX = 16
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
@@ -123,6 +126,10 @@ def load() -> ctypes.CDLL:
         "aca_batch_poll": [P, P, i32, P],
         "aca_batch_advance": [P, P, P, i32, P],
         "aca_batch_members": [P, P, i32, P],
+        "aca_tune": [P, pt, i32, f64, P, P, P, P],
+        "aca_batch_set_order": [P, i32],
+        "aca_server_set_order": [P, i32],
+        "aca_batch_tune": [P, P, P, i32, i32, pt, i32, f64, P, P, P, P],
         "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
         "aca_batch_destroy": [P],
         "aca_server_query": [i32, P],
@@ -164,6 +171,14 @@ def make_tuning(tile=(0, 0, 0), ghost=(-1, -1, -1), max_sweeps=0, block=0) -> Tu
     ghost = list(ghost) + [-1] * (3 - len(ghost))
     return Tuning(ctypes.sizeof(Tuning), (ctypes.c_int32 * 3)(*tile[:3]),
                   (ctypes.c_int32 * 3)(*ghost[:3]), int(max_sweeps), int(block))
+
+
+def _tuning_array(candidates):
+    """(Tuning array or None, count) for the autotuner entry points."""
+    if not candidates:
+        return None, 0
+    arr = (Tuning * len(candidates))(*[make_tuning(**c) for c in candidates])
+    return arr, len(candidates)
 
 
 def abi_version() -> int:
@@ -233,6 +248,18 @@ class Lattice:
         _check(self.lib.aca_get_tuning(self._h, ctypes.byref(t)))
         return {"tile": list(t.tile), "ghost": list(t.ghost), "max_sweeps": t.max_sweeps,
                 "block": t.block}
+
+    def tune(self, dT: float, candidates=None) -> dict:
+        """Advance by slices of dT, one candidate schedule per slice, and keep
+        the fastest (results are the same whichever is chosen)."""
+        cands, n = _tuning_array(candidates)
+        best = ctypes.c_int32(0)
+        count = ctypes.c_int32(0)
+        rates = (ctypes.c_double * TUNE_MAX)()
+        _check(self.lib.aca_tune(self._h, cands, n, float(dT), self._s(), ctypes.byref(best),
+                                 rates, ctypes.byref(count)))
+        return {"best": best.value, "rates_per_ms": list(rates[:count.value]),
+                "tuning": self.tuning()}
 
     def init(self) -> "Lattice":
         _check(self.lib.aca_init(self._h, self._s()))
@@ -308,6 +335,31 @@ class Batch:
         _check(self.lib.aca_batch_get_tuning(self._h, int(dim), ctypes.byref(t)))
         return {"tile": list(t.tile), "ghost": list(t.ghost), "max_sweeps": t.max_sweeps,
                 "block": t.block}
+
+    def tune(self, lattices, T, dim: int, candidates=None, frac: float = 0.02) -> dict:
+        """Advance the lattices (towards horizons T) slice by slice, one
+        candidate schedule for dimension `dim` per slice, and keep the fastest."""
+        lats = list(lattices)
+        Ts = np.asarray(T, dtype=np.float64)
+        handles = (ctypes.c_void_p * len(lats))(*[l._h.value for l in lats])
+        cands, n = _tuning_array(candidates)
+        best = ctypes.c_int32(0)
+        count = ctypes.c_int32(0)
+        rates = (ctypes.c_double * TUNE_MAX)()
+        for l in lats:
+            self._members[l._h.value] = l
+        try:
+            _check(self.lib.aca_batch_tune(self._h, handles, Ts.ctypes.data, len(lats),
+                                           int(dim), cands, n, float(frac), self._s(),
+                                           ctypes.byref(best), rates, ctypes.byref(count)))
+        finally:
+            for l in lats:
+                self._members.pop(l._h.value, None)
+        return {"best": best.value, "rates_per_ms": list(rates[:count.value]),
+                "tuning": self.tuning(dim)}
+
+    def set_order(self, order: int) -> None:
+        _check(self.lib.aca_batch_set_order(self._h, int(order)))
 
     def attach(self, lat: "Lattice", T: float) -> None:
         _check(self.lib.aca_batch_attach(self._h, lat._h, float(T)))
@@ -416,6 +468,9 @@ class Server:
         t = make_tuning(**kw) if kw else None
         _check(self.lib.aca_server_set_tuning(self._h, int(dim),
                                               ctypes.byref(t) if t is not None else None))
+
+    def set_order(self, order: int) -> None:
+        _check(self.lib.aca_server_set_order(self._h, int(order)))
 
     def submit(self, params: dict, T: Optional[float] = None) -> int:
         job = ctypes.c_uint64(0)

@@ -125,10 +125,53 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->ghost[0] = 4; t->ghost[1] = 4;
         t->max_sweeps = 32; t->block = 512;
     } else {
-        t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 16;
+        t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 8;
         t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
         t->max_sweeps = 16; t->block = 512;
     }
+}
+
+int tune_candidates(int dim, aca_tuning *out)
+{
+    // tile sides, ghost width, worklist rounds per visit
+    static const int c1[][3] = {{8192, 64, 512}, {4096, 32, 256}, {16384, 64, 1024},
+                                {8192, 128, 1024}, {2048, 16, 128}};
+    static const int c2[][5] = {{64, 56, 4, 32, 0}, {64, 56, 4, 24, 0}, {64, 56, 4, 48, 0},
+                                {64, 48, 3, 32, 0}, {48, 48, 4, 32, 0}, {96, 40, 4, 32, 0},
+                                {64, 64, 3, 32, 0}, {32, 32, 2, 16, 0}, {64, 56, 2, 16, 0},
+                                {56, 56, 4, 32, 0}};
+    static const int c3[][5] = {{16, 16, 8, 1, 16}, {16, 16, 16, 1, 16}, {16, 16, 8, 1, 12},
+                                {16, 16, 8, 1, 24}, {16, 8, 8, 1, 16}, {8, 8, 8, 1, 8},
+                                {16, 16, 16, 1, 12}, {24, 16, 8, 1, 16}};
+    int n = 0;
+    auto base = [&]() -> aca_tuning & {
+        aca_tuning &t = out[n++];
+        memset(&t, 0, sizeof t);
+        t.struct_size = sizeof t;
+        t.ghost[0] = t.ghost[1] = t.ghost[2] = -1;
+        return t;
+    };
+    if (dim == 1) {
+        for (const auto &c : c1) {
+            aca_tuning &t = base();
+            t.tile[0] = c[0]; t.ghost[0] = c[1]; t.max_sweeps = c[2];
+        }
+    } else if (dim == 2) {
+        for (const auto &c : c2) {
+            aca_tuning &t = base();
+            t.tile[0] = c[0]; t.tile[1] = c[1];
+            t.ghost[0] = t.ghost[1] = c[2];
+            t.max_sweeps = c[3];
+        }
+    } else {
+        for (const auto &c : c3) {
+            aca_tuning &t = base();
+            t.tile[0] = c[0]; t.tile[1] = c[1]; t.tile[2] = c[2];
+            t.ghost[0] = t.ghost[1] = t.ghost[2] = c[3];
+            t.max_sweeps = c[4];
+        }
+    }
+    return n;
 }
 
 aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
@@ -504,6 +547,58 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
     lat->stats.device_ms +=
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
             .count();
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_t n, double dT,
+                              void *stream, int32_t *best, double *rates, int32_t *n_out)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
+    if (!lat->initialized) return fail(ACA_ESTATE, "aca_init (or aca_resume) first");
+    if (!is_finite(dT) || !(dT > 0.0)) return fail(ACA_EINVAL, "dT must be finite and > 0");
+    aca_tuning table[ACA_TUNE_MAX];
+    if (!cands || n <= 0) {
+        n = tune_candidates(lat->p.dim, table);
+        cands = table;
+    }
+    if (n > ACA_TUNE_MAX) return fail(ACA_EINVAL, "at most %d candidates", ACA_TUNE_MAX);
+    const aca_tuning keep = lat->tun;
+    for (int32_t k = 0; k < n; ++k) {
+        aca_status st = aca_set_tuning(lat, &cands[k]);
+        Plan plan;
+        if (st == ACA_OK) st = make_plan(lat, lat->last_T + dT, &plan);
+        if (st != ACA_OK) {
+            lat->tun = keep;
+            return fail(ACA_EINVAL, "candidate %d: %s", k, g_error.c_str());
+        }
+    }
+    aca_status st = aca_set_tuning(lat, &cands[0]);
+    if (st == ACA_OK) st = aca_advance(lat, lat->last_T + 0.5 * dT, stream);
+    double best_rate = -1.0;
+    int32_t best_k = 0;
+    for (int32_t k = 0; k < n && st == ACA_OK; ++k) {
+        st = aca_set_tuning(lat, &cands[k]);
+        if (st != ACA_OK) break;
+        const uint64_t ev0 = lat->stats.events;
+        const double ms0 = lat->stats.device_ms;
+        st = aca_advance(lat, lat->last_T + dT, stream);
+        if (st != ACA_OK) break;
+        const double ms = lat->stats.device_ms - ms0;
+        const double rate = ms > 0.0 ? (double)(lat->stats.events - ev0) / ms : 0.0;
+        if (rates) rates[k] = rate;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best_k = k;
+        }
+    }
+    if (st != ACA_OK) {
+        lat->tun = keep;
+        return st;
+    }
+    lat->tun = cands[best_k];
+    if (best) *best = best_k;
+    if (n_out) *n_out = n;
     return ACA_OK;
 }
 

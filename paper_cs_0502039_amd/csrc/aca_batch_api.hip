@@ -63,6 +63,7 @@ struct Member {
     aca_lattice *lat = nullptr;
     double T = 0.0;
     bool joining = false;
+    uint64_t seq = 0;           // attach order
     uint64_t work = 0;          // arrivals expected: N (T - last T) rate
     uint64_t region_bytes = 0;  // per epoch
     size_t lds = 0;
@@ -97,10 +98,28 @@ struct aca_batch {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double wall_hz = 0.0;
     size_t lds_limit_set = 0;
+    int32_t order = ACA_ORDER_WORK;
+    uint64_t next_seq = 0;
     aca_batch_stats stats;
 };
 
 namespace {
+
+// Automatic knobs of batch members.  Members are often small, and a batch
+// mixes dimensions in one launch, so 3D members take cubic 16^3 tiles (fewer
+// tiles per small lattice than the single-lattice 16x16x8 choice).
+void batch_auto_tuning(int dim, aca_tuning *t)
+{
+    aca_params p;
+    memset(&p, 0, sizeof p);
+    p.dim = dim;
+    auto_tuning(p, t);
+    if (dim == 3) {
+        t->tile[0] = t->tile[1] = t->tile[2] = 16;
+        t->ghost[0] = t->ghost[1] = t->ghost[2] = 1;
+        t->max_sweeps = 16;
+    }
+}
 
 // Tile plan of a batch member: at least two tiles along every direction, so
 // every region has a frozen ring and the pitched-box visit applies.
@@ -111,7 +130,7 @@ aca_status member_plan(const aca_batch *b, const aca_lattice *lat, double T, aca
     aca_tuning t;
     memset(&t, 0, sizeof t);
     t.ghost[0] = t.ghost[1] = t.ghost[2] = -1;
-    auto_tuning(p, &t);
+    batch_auto_tuning(p.dim, &t);
     const aca_tuning &u = b->tun[p.dim];
     for (int d = 0; d < 3; ++d) {
         if (u.tile[d] > 0) t.tile[d] = u.tile[d];
@@ -274,10 +293,7 @@ ACA_EXPORT aca_status aca_batch_get_tuning(const aca_batch *b, int32_t dim, aca_
     if (dim < 1 || dim > 3) return fail(ACA_EINVAL, "dim %d not in 1..3", dim);
     aca_tuning t;
     memset(&t, 0, sizeof t);
-    aca_params p;
-    memset(&p, 0, sizeof p);
-    p.dim = dim;
-    auto_tuning(p, &t);
+    batch_auto_tuning(dim, &t);
     const aca_tuning &u = b->tun[dim];
     for (int d = 0; d < 3; ++d) {
         if (u.tile[d] > 0) t.tile[d] = u.tile[d];
@@ -288,6 +304,15 @@ ACA_EXPORT aca_status aca_batch_get_tuning(const aca_batch *b, int32_t dim, aca_
     t.struct_size = sizeof t;
     t.block = aca::batch_block_size();
     *out = t;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_batch_set_order(aca_batch *b, int32_t order)
+{
+    if (!b) return fail(ACA_EINVAL, "batch is NULL");
+    if (order != ACA_ORDER_WORK && order != ACA_ORDER_ARRIVAL)
+        return fail(ACA_EINVAL, "unknown order %d", order);
+    b->order = order;
     return ACA_OK;
 }
 
@@ -327,6 +352,7 @@ ACA_EXPORT aca_status aca_batch_attach(aca_batch *b, aca_lattice *lat, double T)
     m.lat = lat;
     m.T = T;
     m.joining = true;
+    m.seq = b->next_seq++;
     m.work = (uint64_t)((double)lat->n * (T - lat->last_T) * lat->p.rate);
     m.region_bytes = launch_region_bytes(lat->p.dim, a);
     m.lds = lds;
@@ -366,9 +392,14 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
     uint32_t *h_mem = h_join_start + cap + 1;
     uint32_t *h_mem_start = h_mem + cap;
     std::vector<int> prio = mem;
-    std::stable_sort(prio.begin(), prio.end(), [&](int x, int y) {
-        return b->member[x].work > b->member[y].work;
-    });
+    if (b->order == ACA_ORDER_ARRIVAL)
+        std::sort(prio.begin(), prio.end(), [&](int x, int y) {
+            return b->member[x].seq < b->member[y].seq;
+        });
+    else
+        std::stable_sort(prio.begin(), prio.end(), [&](int x, int y) {
+            return b->member[x].work > b->member[y].work;
+        });
     int dim = b->member[mem[0]].lat->p.dim;
     size_t lds = 0;
     uint32_t njoin = 0, jblocks = 0, mblocks = 0;
@@ -548,6 +579,76 @@ ACA_EXPORT aca_status aca_batch_advance(aca_batch *b, aca_lattice *const *lats, 
     }
     b->finished.clear();
     return result;
+}
+
+ACA_EXPORT aca_status aca_batch_tune(aca_batch *b, aca_lattice *const *lats, const double *T,
+                                     int32_t count, int32_t dim, const aca_tuning *cands,
+                                     int32_t n, double frac, void *stream, int32_t *best,
+                                     double *rates, int32_t *n_out)
+{
+    if (!b) return fail(ACA_EINVAL, "batch is NULL");
+    if (dim < 1 || dim > 3) return fail(ACA_EINVAL, "dim %d not in 1..3", dim);
+    if (count < 1 || !lats || !T) return fail(ACA_EINVAL, "bad lattice list");
+    if (!is_finite(frac) || !(frac > 0.0) || frac >= 0.5)
+        return fail(ACA_EINVAL, "frac must be in (0, 0.5)");
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->member[i].lat) return fail(ACA_ESTATE, "batch already has members");
+    aca_tuning table[ACA_TUNE_MAX];
+    if (!cands || n <= 0) {
+        n = tune_candidates(dim, table);
+        cands = table;
+    }
+    if (n > ACA_TUNE_MAX) return fail(ACA_EINVAL, "at most %d candidates", ACA_TUNE_MAX);
+    for (int32_t k = 0; k < n; ++k)
+        if (cands[k].struct_size != sizeof(aca_tuning))
+            return fail(ACA_EINVAL, "candidate %d: struct_size mismatch", k);
+    for (int32_t i = 0; i < count; ++i) {
+        if (!lats[i]) return fail(ACA_EINVAL, "lattice %d is NULL", i);
+        if (!lats[i]->initialized || lats[i]->attached)
+            return fail(ACA_ESTATE, "lattice %d is not initialised or is attached", i);
+        if (!is_finite(T[i]) || T[i] < lats[i]->last_T)
+            return fail(ACA_EINVAL, "lattice %d: horizon before its last one", i);
+    }
+    const aca_tuning keep = b->tun[dim];
+    std::vector<double> start(count), h(count);
+    for (int32_t i = 0; i < count; ++i) start[i] = lats[i]->last_T;
+    // slice s ends at start + (s + 1) frac (T - start); slice 0 is the warm-up
+    auto slice = [&](int s) -> aca_status {
+        for (int32_t i = 0; i < count; ++i) {
+            h[i] = start[i] + (double)(s + 1) * frac * (T[i] - start[i]);
+            h[i] = std::min(std::max(h[i], lats[i]->last_T), T[i]);
+        }
+        return aca_batch_advance(b, lats, h.data(), count, stream);
+    };
+    if (n + 1 > (int32_t)(1.0 / frac))
+        return fail(ACA_EINVAL, "%d candidates need (n + 1) frac <= 1", n);
+    aca_status st = aca_batch_set_tuning(b, dim, &cands[0]);
+    if (st == ACA_OK) st = slice(0);
+    double best_rate = -1.0;
+    int32_t best_k = 0;
+    for (int32_t k = 0; k < n && st == ACA_OK; ++k) {
+        st = aca_batch_set_tuning(b, dim, &cands[k]);
+        if (st != ACA_OK) break;
+        const aca_batch_stats s0 = b->stats;
+        st = slice(k + 1);
+        if (st != ACA_OK) break;
+        const double ms = b->stats.device_ms - s0.device_ms;
+        const double rate = ms > 0.0 ? (double)(b->stats.events - s0.events) / ms : 0.0;
+        if (rates) rates[k] = rate;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best_k = k;
+        }
+    }
+    if (st != ACA_OK) {
+        b->tun[dim] = keep;
+        return st;
+    }
+    st = aca_batch_set_tuning(b, dim, &cands[best_k]);
+    if (st != ACA_OK) return st;
+    if (best) *best = best_k;
+    if (n_out) *n_out = n;
+    return ACA_OK;
 }
 
 ACA_EXPORT aca_status aca_batch_members(const aca_batch *b, aca_lattice **out, int32_t cap,

@@ -56,6 +56,8 @@ struct Plan {
 };
 
 void auto_tuning(const aca_params &p, aca_tuning *t);
+// The library's candidate schedules for the autotuner (at most ACA_TUNE_MAX).
+int tune_candidates(int dim, aca_tuning *out);
 uint64_t launch_region_bytes(int dim, const aca::VisitArgs &a);
 
 }  // namespace aca_host

@@ -235,30 +235,69 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     for (int j = tid; j < (boxp + 31) / 32; j += nthreads) claim[j] = 0u;
     __syncthreads();
 
+    // Box index j = q0 + P1 (q1 + pitch1 q2) of a cell, decoded with the
+    // reciprocal multipliers (exact: j and the pitches stay below 2^16).
+    auto decode = [&](int j, int *q) {
+        const int row = (int)__umulhi((uint32_t)j, magic1);
+        q[0] = j - row * P1;
+        if (DIM > 2) {
+            q[2] = (int)__umulhi((uint32_t)row, magic2);
+            q[1] = row - q[2] * pitch[1];
+        } else {
+            q[1] = row;
+            q[2] = 0;
+        }
+    };
+    auto is_own = [&](const int *q) {
+        bool own = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) own = own && q[d] >= olo[d] && q[d] < ohi[d];
+        return own;
+    };
+    auto is_inner = [&](const int *q) {
+        bool in = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) in = in && q[d] >= 1 && q[d] <= rin[d];
+        return in;
+    };
+    constexpr int U = 4;    // cells per thread in flight in the load and merge loops
+
     // ---- load the region box from the snapshot; note whether any owned
     // cell still has an arrival before the horizon
     bool due = false;
-    const int nbox = rb[0] * rb[1] * rb[2];
-    for (int j = tid; j < nbox; j += nthreads) {
-        const int q0 = j % rb[0];
-        const int r = j / rb[0];
-        const int q1 = r % rb[1];
-        const int q2 = r / rb[1];
-        const int bi = q0 + P1 * q1 + P12 * q2;
-        const uint32_t gi = tx[q0] + ty[q1] + tz[q2];
-        const unsigned long long key = io.key_in[gi];
-        const unsigned long long tb = io.time_in[gi];
-        ts[bi] = (uint64_t)tb | ((key & 1ull) << 63);
-        const bool in0 = q0 >= 1 && q0 <= rin[0];
-        const bool in1 = DIM < 2 || (q1 >= 1 && q1 <= rin[1]);
-        const bool in2 = DIM < 3 || (q2 >= 1 && q2 <= rin[2]);
-        if (in0 && in1 && in2) {
-            nl[bi] = (uint32_t)(key >> 32);
-            fl[bi] = 0;
-            const bool own = q0 >= olo[0] && q0 < ohi[0] &&
-                             (DIM < 2 || (q1 >= olo[1] && q1 < ohi[1])) &&
-                             (DIM < 3 || (q2 >= olo[2] && q2 < ohi[2]));
-            due = due || (own && (uint64_t)tb < a.horizon_bits);
+    for (int j0 = tid; j0 < boxp; j0 += U * nthreads) {
+        bool ok[U], inn[U], own[U];
+        uint32_t gi[U];
+        unsigned long long key[U], tb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * nthreads;
+            int q[3];
+            decode(min(j, boxp - 1), q);
+            ok[u] = j < boxp && q[0] < rb[0] && q[1] < rb[1] && q[2] < rb[2];
+            inn[u] = is_inner(q);
+            own[u] = is_own(q);
+            gi[u] = tx[q[0]] + ty[q[1]] + tz[q[2]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            key[u] = 0;
+            tb[u] = 0;
+            if (ok[u]) {
+                key[u] = io.key_in[gi[u]];
+                tb[u] = io.time_in[gi[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const int bi = j0 + u * nthreads;
+            ts[bi] = (uint64_t)tb[u] | ((key[u] & 1ull) << 63);
+            if (inn[u]) {
+                nl[bi] = (uint32_t)(key[u] >> 32);
+                fl[bi] = 0;
+                due = due || (own[u] && (uint64_t)tb[u] < a.horizon_bits);
+            }
         }
     }
     const int own_due = __syncthreads_or(due ? 1 : 0);
@@ -293,32 +332,28 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     int rounds = 0;
     if (own_due) {
     // ---- initial scan: every enabled simulated cell, claimed, into list 0
-    for (int base = tid - lane; base < inner; base += nthreads) {
-        const int i = base + lane;
+    for (int base = tid - lane; base < boxp; base += nthreads) {
+        const int j = base + lane;
         bool en = false;
-        int bi = 0;
-        if (i < inner) {
-            int q[3];
-            q[0] = i % rin[0] + 1;
-            const int r = i / rin[0];
-            q[1] = (DIM > 1) ? r % rin[1] + 1 : 0;
-            q[2] = (DIM > 2) ? r / rin[1] + 1 : 0;
-            bi = q[0] + P1 * q[1] + P12 * q[2];
+        const int bi = j;
+        int q[3];
+        decode(min(j, boxp - 1), q);
+        if (j < boxp && is_inner(q)) {
             const uint64_t wc = ldw(&ts[bi]);
             uint64_t tn[Z];
             double tmin = time_of(ldw(&ts[bi + off(1)]));
             tn[0] = 0;
 #pragma unroll
-            for (int j = 0; j < Z; ++j) {
-                tn[j] = ldw(&ts[bi + off(1 + j)]);
-                if (j) tmin = __builtin_fmin(tmin, time_of(tn[j]));
+            for (int k = 0; k < Z; ++k) {
+                tn[k] = ldw(&ts[bi + off(1 + k)]);
+                if (k) tmin = __builtin_fmin(tmin, time_of(tn[k]));
             }
             const double tc = time_of(wc);
             const bool due = tc < horizon_t;
             en = due && tc < tmin;
             if (due && tc == tmin) {
 #pragma unroll
-                for (int j = 0; j < Z; ++j) tn[j] &= kMask;
+                for (int k = 0; k < Z; ++k) tn[k] &= kMask;
                 en = exact(wc & kMask, tn, q);
             }
             ++my_checks;
@@ -485,26 +520,35 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 
     // ---- merge owned copies and moved ghost copies; find due owned cells
     bool live = false;
-    for (int j = tid; j < inner; j += nthreads) {
-        int q[3];
-        q[0] = j % rin[0] + 1;
-        const int r = j / rin[0];
-        q[1] = (DIM > 1) ? r % rin[1] + 1 : 0;
-        q[2] = (DIM > 2) ? r / rin[1] + 1 : 0;
-        const int bi = q[0] + P1 * q[1] + P12 * q[2];
-        bool own = true;
+    for (int j0 = tid; j0 < boxp; j0 += U * nthreads) {
+        bool inn[U], own[U];
+        uint32_t gi[U];
+        unsigned long long key_in[U];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) own = own && q[d] >= olo[d] && q[d] < ohi[d];
-        const uint32_t gi = tx[q[0]] + ty[q[1]] + tz[q[2]];
-        const uint32_t n_copy = nl[bi];
-        const unsigned long long key_in = io.key_in[gi];
-        const uint64_t wd = ts[bi];
-        if (own || n_copy != (uint32_t)(key_in >> 32)) {
-            const unsigned long long f = ((key_in >> 1) & 0x7FFFFFFFull) + fl[bi];
-            atomicMax(&io.key_out[gi], ((unsigned long long)n_copy << 32) | (f << 1) | (wd >> 63));
-            atomicMax(&io.time_out[gi], (unsigned long long)(wd & kMask));
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * nthreads;
+            int q[3];
+            decode(min(j, boxp - 1), q);
+            inn[u] = j < boxp && is_inner(q);
+            own[u] = is_own(q);
+            gi[u] = tx[q[0]] + ty[q[1]] + tz[q[2]];
         }
-        if (own) live = live || (wd & kMask) < horizon;
+#pragma unroll
+        for (int u = 0; u < U; ++u) key_in[u] = inn[u] ? io.key_in[gi[u]] : 0ull;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!inn[u]) continue;
+            const int bi = j0 + u * nthreads;
+            const uint32_t n_copy = nl[bi];
+            const uint64_t wd = ts[bi];
+            if (own[u] || n_copy != (uint32_t)(key_in[u] >> 32)) {
+                const unsigned long long f = ((key_in[u] >> 1) & 0x7FFFFFFFull) + fl[bi];
+                atomicMax(&io.key_out[gi[u]],
+                          ((unsigned long long)n_copy << 32) | (f << 1) | (wd >> 63));
+                atomicMax(&io.time_out[gi[u]], (unsigned long long)(wd & kMask));
+            }
+            if (own[u]) live = live || (wd & kMask) < horizon;
+        }
     }
     atomicAdd(&ctr[6], (int)my_events);
     atomicAdd(&ctr[7], (int)my_flips);

@@ -218,6 +218,8 @@ ACA_EXPORT aca_status aca_server_create(void *d_arena, uint64_t arena_bytes, voi
     srv->alloc.reset(arena_bytes & ~(uint64_t)(kAlign - 1));
     srv->batch = batch;
     srv->max_jobs = max_jobs;
+    // serve jobs in arrival order: a job's wait is bounded by the ones before it
+    aca_batch_set_order(batch, ACA_ORDER_ARRIVAL);
     memset(&srv->stats, 0, sizeof srv->stats);
     srv->stats.struct_size = sizeof(aca_server_stats);
     srv->stats.arena_bytes = srv->alloc.size();
@@ -229,6 +231,12 @@ ACA_EXPORT aca_status aca_server_set_tuning(aca_server *srv, int32_t dim, const 
 {
     if (!srv) return fail(ACA_EINVAL, "server is NULL");
     return aca_batch_set_tuning(srv->batch, dim, t);
+}
+
+ACA_EXPORT aca_status aca_server_set_order(aca_server *srv, int32_t order)
+{
+    if (!srv) return fail(ACA_EINVAL, "server is NULL");
+    return aca_batch_set_order(srv->batch, order);
 }
 
 ACA_EXPORT aca_status aca_server_submit(aca_server *srv, const aca_params *p, double T,

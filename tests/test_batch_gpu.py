@@ -268,3 +268,28 @@ def test_batch_512_full_size(torch):
         lat.close()
     assert total == st["events"]
     batch.close()
+
+
+def test_batch_autotune_keeps_results(torch, mixed_expected):
+    """The batch tuner advances the real lattices slice by slice under each
+    candidate; finishing afterwards gives the oracle's result."""
+    cases, expected = mixed_expected
+    lats = [aca.Lattice(p).init() for p in cases]
+    batch = aca.Batch(len(cases))
+    cands = [dict(tile=(16, 16), ghost=(2, 2), max_sweeps=8),
+             dict(tile=(8, 24), ghost=(1, 3), max_sweeps=3),
+             dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32)]
+    res = batch.tune(lats, [p["T"] for p in cases], 2, cands, frac=0.1)
+    assert 0 <= res["best"] < len(cands)
+    assert len(res["rates_per_ms"]) == len(cands) and min(res["rates_per_ms"]) > 0
+    want_tile = list(cands[res["best"]]["tile"]) + [0]
+    assert res["tuning"]["tile"] == want_tile
+    res3 = batch.tune(lats, [p["T"] for p in cases], 3, None, frac=0.05)   # library set
+    assert len(res3["rates_per_ms"]) >= 4
+    batch.advance(lats, [p["T"] for p in cases])
+    for i, (p, (want, ev, fl)) in enumerate(zip(cases, expected)):
+        assert_same_state(lats[i].read(), want, f"case {i}")
+        assert lats[i].stats()["events"] == ev
+    batch.close()
+    for l in lats:
+        l.close()

@@ -234,3 +234,20 @@ def test_full_size_matches_oracle(torch, name):
     assert st["flips"] == gold["flips"]
     assert int(s.astype(np.int64).sum()) == gold["sum_s"]
     assert digest(s, t, n) == (gold["sha256_s"], gold["sha256_t"], gold["sha256_n"])
+
+
+def test_single_autotune_keeps_results(torch):
+    p = workloads.lattice(2, (300, 200), 0.42, seed=77, T=30.0)
+    lat = aca.Lattice(p).init()
+    cands = [dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32),
+             dict(tile=(32, 32), ghost=(2, 2), max_sweeps=8),
+             dict(tile=(300, 7), ghost=(0, 3), max_sweeps=5)]
+    res = lat.tune(3.0, cands)
+    assert 0 <= res["best"] < 3 and min(res["rates_per_ms"]) > 0
+    assert lat.stats()["last_T"] == pytest.approx(3.5 * 3.0)
+    res = lat.tune(1.0)                 # the library's candidate set
+    assert len(res["rates_per_ms"]) >= 5
+    lat.advance(p["T"])
+    s, t, n, ev, fl = oracle.simulate(p, p["T"])
+    assert_same_state(lat.read(), (s, t, n), "after tuning")
+    lat.close()
