@@ -149,6 +149,23 @@ aca_status aca_resume(aca_lattice *lat, double T_done);
  * arrivals applied since time 0. */
 aca_status aca_advance(aca_lattice *lat, double T, void *stream);
 
+/* aca_advance that also writes output frames (Fig. 3.7): for every k in
+ * [k_first, k_first + nframes) whose time k dt lies in (last horizon, T],
+ * frame k - k_first of d_frames (int8[N] per frame, consecutive, cell order)
+ * receives the spins at time k dt, i.e. after every arrival before k dt.
+ * Frames outside that interval are left untouched.  Each cell writes its own
+ * frames as its arrivals are applied, with no global synchronisation: a
+ * frame is complete when the advance returns. */
+aca_status aca_advance_frames(aca_lattice *lat, double T, double dt, int8_t *d_frames,
+                              int64_t k_first, int64_t nframes, void *stream);
+
+/* Bound the lag between local times (the restriction a finite frame buffer
+ * imposes, Section 4): each launch applies only arrivals before
+ * min(T, t_min + lag), t_min the least pending time of the lattice when the
+ * previous launch loaded it (0 = no bound).  A schedule knob: results do not
+ * change, only the parallelism per launch. */
+aca_status aca_set_lag(aca_lattice *lat, double lag);
+
 aca_status aca_get_stats(const aca_lattice *lat, aca_stats *out);
 
 /* Autotuning on the caller's own work.  Every schedule yields the same

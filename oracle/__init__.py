@@ -183,6 +183,23 @@ def simulate(params, T: float):
     return s, t, n, ev, fl
 
 
+def frames(params, T_start: float, T_end: float, dt: float, k_first: int, nframes: int,
+           s: np.ndarray, t: np.ndarray, n: np.ndarray) -> dict:
+    """Output frames (Fig. 3.7): advance (s, t, n) in place from T_start to T_end
+    and return {k: spins at time k dt} for every k in [k_first, k_first + nframes)
+    with k dt in (T_start, T_end].  The spins at time tau are the state after every
+    arrival before tau, i.e. the state ``run`` leaves at horizon tau."""
+    out = {}
+    for k in range(k_first, k_first + nframes):
+        tau = float(k) * dt
+        if tau <= T_start or tau > T_end:
+            continue
+        run(params, tau, s, t, n)
+        out[k] = s.copy()
+    run(params, T_end, s, t, n)
+    return out
+
+
 def cell_clock(params, cells: np.ndarray, T: float):
     """Per-cell first arrival >= T and arrival count < T, from the cell's draws alone."""
     c = np.ascontiguousarray(cells, dtype=np.uint32)

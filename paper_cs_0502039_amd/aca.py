@@ -29,7 +29,8 @@ EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_server_create", "aca_server_set_tuning", "aca_server_submit",
             "aca_server_step", "aca_server_job", "aca_server_read", "aca_server_release",
             "aca_server_load", "aca_server_get_stats", "aca_server_destroy", "aca_tune",
-            "aca_batch_tune", "aca_batch_set_order", "aca_server_set_order")
+            "aca_batch_tune", "aca_batch_set_order", "aca_server_set_order",
+            "aca_advance_frames", "aca_set_lag")
 ORDER_WORK, ORDER_ARRIVAL = 0, 1
 TUNE_MAX = 16
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -128,6 +129,8 @@ def load() -> ctypes.CDLL:
         "aca_batch_members": [P, P, i32, P],
         "aca_tune": [P, pt, i32, f64, P, P, P, P],
         "aca_batch_set_order": [P, i32],
+        "aca_advance_frames": [P, f64, f64, P, ctypes.c_int64, ctypes.c_int64, P],
+        "aca_set_lag": [P, f64],
         "aca_server_set_order": [P, i32],
         "aca_batch_tune": [P, P, P, i32, i32, pt, i32, f64, P, P, P, P],
         "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
@@ -271,6 +274,20 @@ class Lattice:
     def advance(self, T: float) -> "Lattice":
         _check(self.lib.aca_advance(self._h, float(T), self._s()))
         return self
+
+    def advance_frames(self, T: float, dt: float, frames, k_first: int) -> "Lattice":
+        """Advance to T and fill frames[k] (an (nframes, N) int8 cuda tensor) with
+        the spins at time (k_first + k) dt for the frame times in (last T, T]."""
+        assert frames.dtype == self._torch.int8 and frames.is_contiguous()
+        assert frames.numel() == 0 or frames.shape[-1] == self.n
+        nframes = frames.shape[0] if frames.numel() else 0
+        _check(self.lib.aca_advance_frames(self._h, float(T), float(dt),
+                                           frames.data_ptr() if nframes else None,
+                                           int(k_first), int(nframes), self._s()))
+        return self
+
+    def set_lag(self, lag: float) -> None:
+        _check(self.lib.aca_set_lag(self._h, float(lag)))
 
     def stats(self) -> dict:
         st = Stats()

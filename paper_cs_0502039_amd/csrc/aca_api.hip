@@ -221,6 +221,10 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
     memcpy(&hb, &T, sizeof hb);
     a.horizon_bits = hb;
     a.counters = lat->counters;
+    a.final_bits = hb;
+    a.track_tmin = 0;
+    a.frames = nullptr;
+    a.n_cells = lat->n;
     memcpy(a.thr, lat->thr, sizeof a.thr);
     plan->block = t.block;
     int dev_lds = 0;
@@ -346,6 +350,7 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
     lat->dead = reinterpret_cast<uint8_t *>(sc + sl.dead_off);
     lat->initialized = false;
     lat->attached = false;
+    lat->lag = 0.0;
     lat->last_T = 0.0;
     memset(&lat->tun, 0, sizeof lat->tun);
     lat->tun.struct_size = sizeof(aca_tuning);
@@ -437,7 +442,49 @@ ACA_EXPORT aca_status aca_resume(aca_lattice *lat, double T_done)
     return ACA_OK;
 }
 
+namespace {
+
+struct FrameRequest {
+    int8_t *frames;
+    double dt;
+    long long k0;
+    long long count;
+};
+
+aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void *stream);
+
+}  // namespace
+
 ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
+{
+    return advance_impl(lat, T, nullptr, stream);
+}
+
+ACA_EXPORT aca_status aca_advance_frames(aca_lattice *lat, double T, double dt, int8_t *d_frames,
+                                         int64_t k_first, int64_t nframes, void *stream)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (!is_finite(dt) || !(dt > 0.0)) return fail(ACA_EINVAL, "dt must be finite and > 0");
+    if (nframes < 0 || k_first < 0) return fail(ACA_EINVAL, "negative frame range");
+    if (nframes > 0 && !d_frames) return fail(ACA_EINVAL, "frames buffer is NULL");
+    if (!is_finite((double)(k_first + nframes) * dt))
+        return fail(ACA_EINVAL, "frame times overflow");
+    FrameRequest fr{d_frames, dt, (long long)k_first, (long long)nframes};
+    return advance_impl(lat, T, nframes > 0 ? &fr : nullptr, stream);
+}
+
+ACA_EXPORT aca_status aca_set_lag(aca_lattice *lat, double lag)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
+    if (!is_finite(lag) || lag < 0.0) return fail(ACA_EINVAL, "lag must be finite and >= 0");
+    lat->lag = lag;
+    return ACA_OK;
+}
+
+namespace {
+
+aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void *stream)
 {
     if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
     if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
@@ -464,6 +511,33 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
 
     // caller state -> snapshot 0; snapshot 1 starts below every copy (zero)
     HIP_TRY(hipMemsetAsync(lat->counters, 0, 8 * kCounterWords, s));
+    // Under a lag bound each launch applies only arrivals before
+    // min(T, t_min + lag), t_min the least pending time the previous launch
+    // saw when it loaded the lattice (all times are >= the last horizon
+    // before the first launch).  Launches then go one at a time.
+    const bool lagged = lat->lag > 0.0;
+    double t_min = lat->last_T;
+    auto lag_horizon = [&]() {
+        const double h = std::min(T, t_min + lat->lag);
+        uint64_t b;
+        memcpy(&b, &h, sizeof b);
+        return b;
+    };
+    if (lagged) {
+        // both slots' least-pending-time words start above every time
+        for (int slot = 0; slot < 2; ++slot)
+            HIP_TRY(hipMemsetAsync(lat->counters + slot * kSlotWords + aca::kTminBits, 0xFF, 8,
+                                   s));
+        plan.a.track_tmin = 1;
+        plan.a.horizon_bits = lag_horizon();
+    }
+    if (fr) {
+        plan.a.frames = fr->frames;
+        plan.a.frame_dt = fr->dt;
+        plan.a.frame_k0 = fr->k0;
+        plan.a.nframes = fr->count;
+        HIP_TRY(aca::launch_frames_init(plan.a, lat->s, lat->t, lat->last_T, T, s));
+    }
     HIP_TRY(aca::launch_pack(lat->n, lat->s, lat->t, lat->cnt, lat->key[0], lat->time[0],
                              lat->counters + kSumStart, s));
     HIP_TRY(hipMemsetAsync(lat->key[1], 0, 8 * lat->n, s));
@@ -498,12 +572,12 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
     const uint64_t max_launches = 100000;
     aca_status est = enqueue(0);
     if (est != ACA_OK) return est;
-    uint64_t enqueued = 1, prev_live = tiles, k = 0;
+    uint64_t enqueued = 1, prev_live = tiles, k = 0, idle = 0;
     for (;; ++k) {
         if (k + 1 >= max_launches)
             return fail(ACA_ENOPROGRESS, "horizon not reached after %llu launches",
                         (unsigned long long)k + 1);
-        if (enqueued == k + 1 && prev_live * 8 > tiles) {
+        if (!lagged && enqueued == k + 1 && prev_live * 8 > tiles) {
             est = enqueue(k + 1);
             if (est != ACA_OK) return est;
             ++enqueued;
@@ -522,11 +596,20 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
         S.sweeps += hc[aca::kSweeps];
         S.cell_checks += hc[aca::kChecks];
         if (hc[aca::kLiveTiles] == 0) break;
-        if (hc[aca::kEvents] + hc[aca::kGhostEvents] == 0)
+        // under a lag bound one launch may find nothing before its horizon
+        // (the least pending time it was set from was stale); the next one
+        // starts from a fresh least time
+        idle = (hc[aca::kEvents] + hc[aca::kGhostEvents] == 0) ? idle + 1 : 0;
+        if (idle > (lat->lag > 0.0 ? 2 : 0))
             return fail(ACA_ENOPROGRESS, "a launch applied no arrival while %llu tiles "
                         "still had arrivals before the horizon",
                         (unsigned long long)hc[aca::kLiveTiles]);
         prev_live = hc[aca::kLiveTiles];
+        if (lagged) {
+            const unsigned long long tb = hc[aca::kTminBits];
+            if (tb != ~0ull) memcpy(&t_min, &tb, sizeof t_min);
+            plan.a.horizon_bits = lag_horizon();
+        }
         if (enqueued == k + 1) {
             est = enqueue(k + 1);
             if (est != ACA_OK) return est;
@@ -549,6 +632,8 @@ ACA_EXPORT aca_status aca_advance(aca_lattice *lat, double T, void *stream)
             .count();
     return ACA_OK;
 }
+
+}  // namespace
 
 ACA_EXPORT aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_t n, double dT,
                               void *stream, int32_t *best, double *rates, int32_t *n_out)

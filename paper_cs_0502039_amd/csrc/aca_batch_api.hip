@@ -161,6 +161,8 @@ aca_status member_plan(const aca_batch *b, const aca_lattice *lat, double T, aca
     uint64_t hb;
     memcpy(&hb, &T, sizeof hb);
     a->horizon_bits = hb;
+    a->final_bits = hb;          // no lag bound and no frames in a batch
+    a->n_cells = lat->n;
     a->dead = lat->dead;
     memcpy(a->thr, lat->thr, sizeof a->thr);
     const uint64_t tiles = (uint64_t)a->ntiles[0] * a->ntiles[1] * a->ntiles[2];

@@ -82,6 +82,7 @@ struct aca_lattice {
     unsigned long long *host_ctr;   // pinned, mapped, kCounterWords words
     unsigned long long *host_ctr_dev;   // its device address
     bool attached;                  // member of a batch: advanced by it only
+    double lag;                     // lag bound (0: none)
 };
 
 namespace aca_host {

@@ -14,6 +14,7 @@ enum Counter : int {
     kLiveTiles = 3,     // tiles with an owned cell still before the horizon
     kSweeps = 4,        // worklist rounds summed over tile visits
     kChecks = 5,        // enabling tests evaluated
+    kTminBits = 6,      // least pending time of the owned cells at load (bits)
     kNumCounters = 8
 };
 
@@ -49,7 +50,41 @@ struct VisitArgs {
     unsigned int *done_blocks;            // ticket counter of this slot
     uint8_t *dead;                        // per tile: owned cells final in both snapshots
     uint64_t thr[14];
+    // The advance's horizon T: a cell whose pending time is at or past it is
+    // final.  `horizon_bits` above bounds the arrivals this launch may apply;
+    // it equals final_bits unless a lag bound is set (then the host sets it
+    // per launch to min(T, least pending time + lag), and every block adds
+    // the least pending time of its owned cells to the kTminBits counter).
+    uint64_t final_bits;
+    int32_t track_tmin;
+    // Output frames (Fig. 3.7): frame k holds the spins at time k * frame_dt
+    // for k in [frame_k0, frame_k0 + nframes), int8 per cell, cell order.
+    int8_t *frames;                       // NULL: no frames
+    double frame_dt;
+    long long frame_k0;
+    long long nframes;
+    uint64_t n_cells;
 };
+
+// Write `spin` into every frame whose time k dt lies in (t_lo, t_hi]: the
+// cell holds that spin from just after t_lo up to and including t_hi.  Every
+// copy of a cell writes the same values (all copies follow the one
+// trajectory), so concurrent writers agree.
+__device__ __forceinline__ void capture_frames(
+    int8_t *frames, double dt, long long k0, long long nframes, uint64_t n_cells, uint32_t gi,
+    double t_lo, double t_hi, int8_t spin)
+{
+    const double q = t_lo / dt;
+    if (!(q < 9.0e18)) return;            // beyond any representable frame index
+    long long k = (long long)__builtin_floor(q);
+    if (k < k0) k = k0;
+    // the quotient may be off by one either way: settle on exact comparisons
+    while ((double)k * dt <= t_lo) ++k;
+    while (k > k0 && (double)(k - 1) * dt > t_lo) --k;
+    const long long kend = k0 + nframes;
+    for (; k < kend && (double)k * dt <= t_hi; ++k)
+        frames[(uint64_t)(k - k0) * n_cells + gi] = spin;
+}
 
 // Called by thread 0 of every block of a visit launch after it has added its
 // counters.  The last block to finish (ticket ntiles - 1) publishes the slot's
@@ -66,8 +101,8 @@ __device__ inline void finish_visit_block(const VisitArgs &a, unsigned int ntile
                 __hip_atomic_load(&a.counters[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.host_counters[i], v, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&a.counters[i], 0ull, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.counters[i], i == kTminBits ? ~0ull : 0ull,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __hip_atomic_store(a.done_blocks, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence_system();
@@ -106,6 +141,11 @@ hipError_t launch_pack(uint64_t n_cells, const int8_t *s, const double *t,
 hipError_t launch_unpack(uint64_t n_cells, const unsigned long long *key,
                          const unsigned long long *time, int8_t *s, double *t,
                          uint32_t *n, unsigned long long *sums, hipStream_t stream);
+
+// Frames at times in (T0, min(t(c), T)] get each cell's spin at the start of
+// an advance from T0 to T (before any arrival of the advance is applied).
+hipError_t launch_frames_init(const VisitArgs &a, const int8_t *s, const double *t, double T0,
+                              double T, hipStream_t stream);
 
 hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out,
                          uint64_t count, hipStream_t stream);

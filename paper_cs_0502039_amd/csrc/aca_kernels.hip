@@ -235,7 +235,9 @@ __device__ __forceinline__ void wave_append(bool want, uint16_t value, uint16_t 
     }
 }
 
-template <int DIM>
+// FRAMES: capture output frames as arrivals are applied (its own
+// instantiation, so the visit without frames carries none of its registers).
+template <int DIM, bool FRAMES>
 __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -312,7 +314,11 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
 
     // ---- load the region box from the snapshot; note whether any owned
     // cell still has an arrival before the horizon
+    __shared__ unsigned long long tmin_block;    // least owned pending time (lag bound)
+    if (tid == 0) tmin_block = ~0ull;
+    __syncthreads();
     bool due = false;
+    uint64_t tmin_own = ~0ull;
     for (int j = tid; j < R.box; j += nthreads) {
         int q[3];
         q[0] = j % rbox[0];
@@ -341,13 +347,21 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
 #pragma unroll
             for (int d = 0; d < DIM; ++d)
                 own_cell = own_cell && pi[d] >= R.olo[d] && pi[d] < R.ohi[d];
-            due = due || (own_cell && (uint64_t)tb < a.horizon_bits);
+            due = due || (own_cell && (uint64_t)tb < a.final_bits);
+            if (own_cell && (uint64_t)tb < tmin_own) tmin_own = (uint64_t)tb;
         }
     }
+    if (a.track_tmin && tmin_own != ~0ull) atomicMin(&tmin_block, tmin_own);
     const int own_due = __syncthreads_or(due ? 1 : 0);
+    if (a.track_tmin && tid == 0 && tmin_block != ~0ull)
+        atomicMin(&a.counters[kTminBits], tmin_block);
 
     constexpr int Z = 2 * DIM;
+    // arrivals before this launch's horizon may be applied; cells at or past
+    // the advance's horizon are final
     const uint64_t horizon = a.horizon_bits;
+    const uint64_t final_bits = a.final_bits;
+    const double final_t = __longlong_as_double((long long)final_bits);
     const bool unit_rate = a.unit_rate != 0;
     uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
 
@@ -417,6 +431,9 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
                 const double tnow = __longlong_as_double((long long)(wd & kTimeMask));
                 const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
                 const uint64_t sign = (wd & kSignBit) ^ (flip ? kSignBit : 0ull);
+                if (FRAMES)
+                    capture_frames(a.frames, a.frame_dt, a.frame_k0, a.nframes, a.n_cells, R.global_index(p), tnow, __builtin_fmin(tnext, final_t),
+                                   sign ? (int8_t)-1 : (int8_t)1);
                 nl[ii] = k + 1u;
                 fl[ii] = (uint16_t)(fl[ii] + (flip ? 1u : 0u));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -493,7 +510,7 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
             atomicMax(&a.key_out[gi], key);
             atomicMax(&a.time_out[gi], (unsigned long long)(wd & kTimeMask));
         }
-        if (own_cell) live = live || (wd & kTimeMask) < horizon;
+        if (own_cell) live = live || (wd & kTimeMask) < final_bits;
     }
     // ---- counters
     atomicAdd(&ctr[6], (int)my_events);
@@ -569,6 +586,17 @@ __global__ void unpack_kernel(uint64_t n_cells, const unsigned long long *key,
     block_add(&sums[1], acc_f);
 }
 
+// ----------------------------------------------------------------- frames
+
+__global__ void frames_init_kernel(VisitArgs a, const int8_t *s, const double *t, double T0,
+                                   double T)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.n_cells;
+         c += stride)
+        capture_frames(a.frames, a.frame_dt, a.frame_k0, a.nframes, a.n_cells, (uint32_t)c, T0, __builtin_fmin(t[c], T), s[c]);
+}
+
 // ----------------------------------------------------------------- checks
 
 __global__ void philox_kernel(const uint32_t *ctr, uint32_t key_lo, uint32_t key_hi,
@@ -631,22 +659,32 @@ hipError_t launch_init(int dim, const int32_t *L, uint64_t n_cells, uint32_t key
     return hipGetLastError();
 }
 
+template <bool FRAMES>
+void launch_generic(int dim, const VisitArgs &a, unsigned tiles, int block, size_t lds,
+                    hipStream_t stream)
+{
+    switch (dim) {
+    case 1:
+        hipLaunchKernelGGL((visit_kernel<1, FRAMES>), dim3(tiles), dim3(block), lds, stream, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL((visit_kernel<2, FRAMES>), dim3(tiles), dim3(block), lds, stream, a);
+        break;
+    default:
+        hipLaunchKernelGGL((visit_kernel<3, FRAMES>), dim3(tiles), dim3(block), lds, stream, a);
+        break;
+    }
+}
+
 hipError_t launch_visit(int dim, const VisitArgs &a, int block, size_t lds,
                         hipStream_t stream)
 {
     const unsigned tiles = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                            (unsigned)a.ntiles[2];
-    switch (dim) {
-    case 1:
-        hipLaunchKernelGGL(visit_kernel<1>, dim3(tiles), dim3(block), lds, stream, a);
-        break;
-    case 2:
-        hipLaunchKernelGGL(visit_kernel<2>, dim3(tiles), dim3(block), lds, stream, a);
-        break;
-    default:
-        hipLaunchKernelGGL(visit_kernel<3>, dim3(tiles), dim3(block), lds, stream, a);
-        break;
-    }
+    if (a.frames)
+        launch_generic<true>(dim, a, tiles, block, lds, stream);
+    else
+        launch_generic<false>(dim, a, tiles, block, lds, stream);
     return hipGetLastError();
 }
 
@@ -681,15 +719,27 @@ hipError_t launch_unpack(uint64_t n_cells, const unsigned long long *key,
 
 hipError_t set_visit_lds_limit(size_t bytes)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)visit_kernel<1>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)visit_kernel<2>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)visit_kernel<3>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *fns[6] = {(const void *)visit_kernel<1, false>,
+                          (const void *)visit_kernel<2, false>,
+                          (const void *)visit_kernel<3, false>,
+                          (const void *)visit_kernel<1, true>,
+                          (const void *)visit_kernel<2, true>,
+                          (const void *)visit_kernel<3, true>};
+    for (const void *f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_frames_init(const VisitArgs &a, const int8_t *s, const double *t, double T0,
+                              double T, hipStream_t stream)
+{
+    const unsigned block = 256;
+    hipLaunchKernelGGL(frames_init_kernel, dim3(reduce_grid(a.n_cells, block)), dim3(block), 0,
+                       stream, a, s, t, T0, T);
+    return hipGetLastError();
 }
 
 hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out,

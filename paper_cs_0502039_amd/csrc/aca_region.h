@@ -163,7 +163,9 @@ struct Snapshots {
     unsigned long long *time_out;
 };
 
-template <int DIM>
+// FRAMES: capture output frames as arrivals are applied (a separate
+// instantiation, so the visit without frames carries none of its registers).
+template <int DIM, bool FRAMES = false>
 __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Snapshots io,
                                                     uint32_t tile, unsigned char *lds)
 {
@@ -224,6 +226,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 
     // ---- tables: global offsets of box rows/columns/planes; clear claims
     if (tid < 2 * (Z + 1)) thr[tid] = a.thr[tid];
+    if (tid == 15) thr[15] = ~0ull;     // least owned pending time (lag bound)
     if (tid < 16) ctr[tid] = 0;
     for (int j = tid; j < rb[0]; j += nthreads) tx[j] = (uint32_t)wrap_into(org[0] + j, side[0]);
     for (int j = tid; j < rb[1]; j += nthreads)
@@ -265,6 +268,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // ---- load the region box from the snapshot; note whether any owned
     // cell still has an arrival before the horizon
     bool due = false;
+    uint64_t tmin_own = ~0ull;
     for (int j0 = tid; j0 < boxp; j0 += U * nthreads) {
         bool ok[U], inn[U], own[U];
         uint32_t gi[U];
@@ -296,14 +300,22 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             if (inn[u]) {
                 nl[bi] = (uint32_t)(key[u] >> 32);
                 fl[bi] = 0;
-                due = due || (own[u] && (uint64_t)tb[u] < a.horizon_bits);
+                due = due || (own[u] && (uint64_t)tb[u] < a.final_bits);
+                if (own[u] && (uint64_t)tb[u] < tmin_own) tmin_own = (uint64_t)tb[u];
             }
         }
     }
+    if (a.track_tmin && tmin_own != ~0ull) atomicMin(&thr[15], tmin_own);
     const int own_due = __syncthreads_or(due ? 1 : 0);
+    if (a.track_tmin && tid == 0 && thr[15] != ~0ull)
+        atomicMin(&a.counters[kTminBits], (unsigned long long)thr[15]);
 
+    // arrivals before this launch's horizon may be applied; cells at or past
+    // the advance's horizon are final
     const uint64_t horizon = a.horizon_bits;
-    const double horizon_t = __longlong_as_double((long long)a.horizon_bits);
+    const double horizon_t = __longlong_as_double((long long)horizon);
+    const uint64_t final_bits = a.final_bits;
+    const double final_t = __longlong_as_double((long long)final_bits);
     const bool unit_rate = a.unit_rate != 0;
     uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
 
@@ -416,6 +428,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
                 const uint64_t wnew = (uint64_t)__double_as_longlong(tnext) |
                                       ((W[0] & kSign) ^ (flip ? kSign : 0ull));
+                if (FRAMES)
+                    capture_frames(a.frames, a.frame_dt, a.frame_k0, a.nframes, a.n_cells, gidx, tnow, __builtin_fmin(tnext, final_t),
+                                   (wnew >> 63) ? (int8_t)-1 : (int8_t)1);
                 nl[bi] = kn + 1u;
                 fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -547,7 +562,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                           ((unsigned long long)n_copy << 32) | (f << 1) | (wd >> 63));
                 atomicMax(&io.time_out[gi[u]], (unsigned long long)(wd & kMask));
             }
-            if (own[u]) live = live || (wd & kMask) < horizon;
+            if (own[u]) live = live || (wd & kMask) < final_bits;
         }
     }
     atomicAdd(&ctr[6], (int)my_events);

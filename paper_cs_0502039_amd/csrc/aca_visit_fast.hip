@@ -12,14 +12,14 @@
 namespace aca {
 namespace {
 
-template <int DIM>
+template <int DIM, bool FRAMES>
 __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                                       (unsigned)a.ntiles[2];
     const region::Snapshots io{a.key_in, a.time_in, a.key_out, a.time_out};
-    const region::RegionTally r = region::visit_region<DIM>(a, io, blockIdx.x, lds);
+    const region::RegionTally r = region::visit_region<DIM, FRAMES>(a, io, blockIdx.x, lds);
     if (threadIdx.x == 0) {
         if (!r.skipped) {
             unsigned long long *gc = a.counters;
@@ -48,35 +48,52 @@ int visit_fast_box(int dim, const VisitArgs &a)
     return box;
 }
 
+template <bool FRAMES>
+void launch_fast(int dim, const VisitArgs &a, unsigned tiles, int block, size_t lds,
+                 hipStream_t stream)
+{
+    switch (dim) {
+    case 1:
+        hipLaunchKernelGGL((visit_fast_kernel<1, FRAMES>), dim3(tiles), dim3(block), lds,
+                           stream, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL((visit_fast_kernel<2, FRAMES>), dim3(tiles), dim3(block), lds,
+                           stream, a);
+        break;
+    default:
+        hipLaunchKernelGGL((visit_fast_kernel<3, FRAMES>), dim3(tiles), dim3(block), lds,
+                           stream, a);
+        break;
+    }
+}
+
 hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
                              hipStream_t stream)
 {
     const unsigned tiles = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                            (unsigned)a.ntiles[2];
-    switch (dim) {
-    case 1:
-        hipLaunchKernelGGL(visit_fast_kernel<1>, dim3(tiles), dim3(block), lds, stream, a);
-        break;
-    case 2:
-        hipLaunchKernelGGL(visit_fast_kernel<2>, dim3(tiles), dim3(block), lds, stream, a);
-        break;
-    default:
-        hipLaunchKernelGGL(visit_fast_kernel<3>, dim3(tiles), dim3(block), lds, stream, a);
-        break;
-    }
+    if (a.frames)
+        launch_fast<true>(dim, a, tiles, block, lds, stream);
+    else
+        launch_fast<false>(dim, a, tiles, block, lds, stream);
     return hipGetLastError();
 }
 
 hipError_t set_visit_fast_lds_limit(size_t bytes)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)visit_fast_kernel<1>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)visit_fast_kernel<2>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)visit_fast_kernel<3>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *fns[6] = {(const void *)visit_fast_kernel<1, false>,
+                          (const void *)visit_fast_kernel<2, false>,
+                          (const void *)visit_fast_kernel<3, false>,
+                          (const void *)visit_fast_kernel<1, true>,
+                          (const void *)visit_fast_kernel<2, true>,
+                          (const void *)visit_fast_kernel<3, true>};
+    for (const void *f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace aca

@@ -495,3 +495,25 @@ def test_ghost_copies_must_be_merged():
                            merge_ghosts=False)
     assert np.array_equal(t, t2) and np.array_equal(n, n2)   # clocks never depend on spins
     assert not np.array_equal(s, s2)
+
+
+def test_frames_beta_zero_metropolis_closed_form():
+    """Fig. 3.7 frames at beta = 0 under Metropolis: every arrival flips, so the
+    spin at time tau is s0 (-1)^n(tau), with n(tau) the closed-form count of the
+    cell's arrivals before tau; the frame at the horizon is the final state."""
+    p = P(2, (23, 17), 0.0, "metropolis", seed=31)
+    s, t, n = oracle.init(p)
+    s0 = s.copy()
+    cells = np.arange(s.size, dtype=np.uint32)
+    fr = oracle.frames(p, 0.0, 6.0, 0.75, 0, 12, s, t, n)
+    assert sorted(fr) == list(range(1, 9))          # 0.75 .. 6.0; k = 0 is not after 0
+    for k, img in fr.items():
+        _, nk = oracle.cell_clock(p, cells, k * 0.75)
+        want = (s0 * np.where(nk % 2 == 1, -1, 1)).astype(np.int8)
+        assert np.array_equal(img, want), k
+    assert np.array_equal(fr[8], s)
+    # continuing from the horizon: the next frames, and none before 6.0 again
+    fr2 = oracle.frames(p, 6.0, 9.0, 0.75, 0, 20, s, t, n)
+    assert sorted(fr2) == list(range(9, 13))
+    _, nk = oracle.cell_clock(p, cells, 9.0)
+    assert np.array_equal(fr2[12], (s0 * np.where(nk % 2 == 1, -1, 1)).astype(np.int8))

@@ -251,3 +251,87 @@ def test_single_autotune_keeps_results(torch):
     s, t, n, ev, fl = oracle.simulate(p, p["T"])
     assert_same_state(lat.read(), (s, t, n), "after tuning")
     lat.close()
+
+
+# ------------------------------------------------------------ frames and lag bound
+
+FRAME_CASES = [
+    workloads.lattice(2, (200, 131), 0.41, seed=61, T=9.0),       # pitched-box kernel
+    workloads.lattice(2, (37, 23), 0.3, "metropolis", h=0.2, seed=62, T=7.0),   # one region
+    workloads.lattice(3, (40, 33, 21), 0.2, "metropolis", h=0.1, init="plus", seed=63, T=4.0),
+    workloads.lattice(1, (5000,), 0.5, seed=64, T=6.0),
+]
+
+
+@pytest.mark.parametrize("params", FRAME_CASES, ids=lambda p: f"{p['dim']}d-{p['L']}")
+def test_frames_match_oracle(torch, params):
+    """Fig. 3.7 output: every frame equals the oracle's state at its time; a
+    second advance continues the frame sequence."""
+    dt = 0.55
+    T1 = params["T"] * 0.6
+    T2 = params["T"]
+    lat = aca.Lattice(params).init()
+    n = lat.n
+    frames = torch.full((40, n), 7, dtype=torch.int8, device="cuda")
+    lat.advance_frames(T1, dt, frames, 0)
+    lat.advance_frames(T2, dt, frames, 0)
+    got = frames.cpu().numpy()
+    s, t, c = oracle.init(params)
+    want = oracle.frames(params, 0.0, T1, dt, 0, 40, s, t, c)
+    want.update(oracle.frames(params, T1, T2, dt, 0, 40, s, t, c))
+    for k in range(40):
+        if k in want:
+            assert np.array_equal(got[k], want[k]), f"frame {k}"
+        else:
+            assert (got[k] == 7).all(), f"frame {k} outside (0, T] was written"
+    assert_same_state(lat.read(), (s, t, c), "final state")
+    lat.close()
+
+
+@pytest.mark.parametrize("lag", [0.05, 0.3, 1.0, 4.0])
+@pytest.mark.parametrize("params", FRAME_CASES[:3], ids=lambda p: f"{p['dim']}d-{p['L']}")
+def test_lag_bound_keeps_results(torch, params, lag):
+    """A lag bound only restricts which arrivals each launch may apply."""
+    lat = aca.Lattice(params).init()
+    lat.set_lag(lag)
+    lat.advance(params["T"] * 0.5).advance(params["T"])
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    assert_same_state(lat.read(), (s, t, n), f"lag {lag}")
+    st = lat.stats()
+    assert st["events"] == ev and st["flips"] == fl
+    # a tight bound needs more launches than no bound
+    free = aca.Lattice(params).init().advance(params["T"])
+    if lag <= 0.3:
+        assert st["launches"] > free.stats()["launches"]
+    free.close()
+    lat.close()
+
+
+def test_frames_with_lag_bound(torch):
+    params = FRAME_CASES[0]
+    lat = aca.Lattice(params).init()
+    lat.set_lag(0.5)
+    frames = torch.zeros((20, lat.n), dtype=torch.int8, device="cuda")
+    lat.advance_frames(params["T"], 0.5, frames, 1)
+    s, t, c = oracle.init(params)
+    want = oracle.frames(params, 0.0, params["T"], 0.5, 1, 20, s, t, c)
+    got = frames.cpu().numpy()
+    for k, img in want.items():
+        assert np.array_equal(got[k - 1], img), f"frame {k}"
+    lat.close()
+
+
+def test_frames_and_lag_argument_errors(torch):
+    params = FRAME_CASES[1]
+    lat = aca.Lattice(params).init()
+    with pytest.raises(aca.AcaError):
+        lat.set_lag(-1.0)
+    with pytest.raises(aca.AcaError):
+        lat.set_lag(float("nan"))
+    frames = torch.zeros((2, lat.n), dtype=torch.int8, device="cuda")
+    for dt in (0.0, -1.0, float("inf")):
+        with pytest.raises(aca.AcaError):
+            lat.advance_frames(1.0, dt, frames, 0)
+    with pytest.raises(aca.AcaError):
+        lat.advance_frames(1.0, 0.5, frames, -1)
+    lat.close()
