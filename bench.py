@@ -249,6 +249,47 @@ def bench_served(arena_gib: float, max_jobs: int, budget_ms: float, count: int) 
             "arena_peak_gib": st["arena_peak"] / (1 << 30), "queued_peak": st["queued_peak"]}
 
 
+def bench_lag(lags, T: float = 50.0, frame_dt: float = 5.0) -> dict:
+    """The bounded-lag experiment (Section 4, efficiency against the lag bound)
+    on the 4096^2 critical lattice to T = 50: arrivals per second, launches and
+    the fraction of enabling tests that found an enabled cell, per lag bound;
+    plus the cost of writing output frames every frame_dt."""
+    import torch
+    from paper_cs_0502039_amd import aca, workloads
+    params = workloads.square_4096()
+    lat = aca.Lattice(params)
+    lat.init().advance(T)           # warm-up
+    rows = []
+    for lag in lags:
+        lat.set_lag(lag)
+        lat.init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.advance(T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = lat.stats()
+        rows.append({"lag": lag if lag > 0 else None, "ms": dt * 1e3,
+                     "spin_updates_per_s": st["events"] / dt, "launches": st["launches"],
+                     "enabled_per_check": (st["events"] + st["ghost_events"])
+                     / max(1, st["cell_checks"])})
+        log(f"lag {lag}: {dt * 1e3:.1f} ms, {st['launches']} launches")
+    lat.set_lag(0.0)
+    nframes = int(T / frame_dt)
+    frames = torch.empty((nframes, lat.n), dtype=torch.int8, device="cuda")
+    lat.init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.advance_frames(T, frame_dt, frames, 1)
+    torch.cuda.synchronize()
+    dt_f = time.perf_counter() - t0
+    lat.close()
+    base = rows[0]["ms"] if rows and rows[0]["lag"] is None else None
+    return {"workload": "square_4096", "T": T, "rows": rows,
+            "frames": {"dt": frame_dt, "count": nframes, "ms": dt_f * 1e3,
+                       "ms_without": base}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,7 +309,7 @@ def main() -> int:
                     help="keep the automatic schedules instead of tuning on the workload")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--only", choices=("single", "batched", "served"), default=None)
+    ap.add_argument("--only", choices=("single", "batched", "served", "lag"), default=None)
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-arena-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=512)
@@ -287,6 +328,10 @@ def main() -> int:
     if args.only == "batched":
         print(json.dumps({"batched": bench_batched(args.steps, args.warmup,
                                                    not args.no_autotune)}), flush=True)
+        return 0
+    if args.only == "lag":
+        print(json.dumps({"lag": bench_lag([0.0, 16.0, 8.0, 4.0, 2.0, 1.0, 0.5, 0.3])}),
+              flush=True)
         return 0
     if args.only == "served":
         print(json.dumps({"served": bench_served(args.serve_arena_gib, args.serve_slots,
