@@ -54,7 +54,7 @@ def digest(s, t, n):
             hashlib.sha256(n.astype("<u4").tobytes()).hexdigest())
 
 
-VISIT_SOURCES = ("aca_device.h", "aca_internal.h", "aca_visit_fast.hip")
+VISIT_SOURCES = ("aca_device.h", "aca_internal.h", "aca_region.h", "aca_visit_fast.hip")
 
 
 def kernel_source_digest() -> str:
@@ -296,7 +296,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="square_4096")
-    ap.add_argument("--cpu-sample-T", type=float, default=0.5)
+    ap.add_argument("--cpu-sample-T", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--tile", type=int, nargs="*", default=None)
