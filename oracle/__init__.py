@@ -17,6 +17,10 @@ Lattice parameters are plain dicts, as produced by the workload generators::
     {"dim": 2, "L": [64, 64], "J": 1.0, "h": 0.0, "beta": 0.4, "rate": 1.0,
      "rule": "glauber" | "metropolis", "init": "random" | "plus" | "minus",
      "seed": 1}
+
+An optional "range": q > 1 selects the q-th degree neighbourhood (Section 3,
+after Fig. 3.5): the rule reads the spins of every cell within lattice
+distance q (every side must exceed 2q).
 """
 from __future__ import annotations
 
@@ -76,6 +80,11 @@ def lib() -> ctypes.CDLL:
             L.oracle_run.argtypes = [i32, P, f64, f64, f64, f64, i32, u64, f64,
                                      P, P, P, P]
             L.oracle_run.restype = i64
+            L.oracle_thresholds_range.argtypes = [i32, i32, f64, f64, f64, i32, P]
+            L.oracle_thresholds_range.restype = i32
+            L.oracle_run_range.argtypes = [i32, P, i32, f64, f64, f64, f64, i32, u64, f64,
+                                           P, P, P, P]
+            L.oracle_run_range.restype = i64
             L.oracle_cell_clock.argtypes = [u64, f64, P, i64, f64, P, P]
             L.oracle_cell_clock.restype = None
             L.oracle_run_rounds.argtypes = [i32, P, f64, f64, f64, f64, i32, u64,
@@ -136,12 +145,18 @@ def ln2_split() -> tuple[float, float]:
     return hi.value, lo.value
 
 
-def thresholds(dim: int, J: float, h: float, beta: float, rule: str) -> np.ndarray:
-    out = np.zeros(14, dtype=np.uint64)
-    k = lib().oracle_thresholds(int(dim), float(J), float(h), float(beta),
-                                RULES[rule], _p(out))
+def thresholds(dim: int, J: float, h: float, beta: float, rule: str,
+               q: int = 1) -> np.ndarray:
+    """Flip thresholds; q > 1 for the q-th degree neighbourhood's table."""
+    out = np.zeros(130, dtype=np.uint64)
+    if q > 1:
+        k = lib().oracle_thresholds_range(int(dim), int(q), float(J), float(h),
+                                          float(beta), RULES[rule], _p(out))
+    else:
+        k = lib().oracle_thresholds(int(dim), float(J), float(h), float(beta),
+                                    RULES[rule], _p(out))
     if k < 0:
-        raise ValueError("bad dimension")
+        raise ValueError("bad dimension or range")
     return out[:k].copy()
 
 
@@ -163,8 +178,20 @@ def init(params) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
 
 
 def run(params, T: float, s: np.ndarray, t: np.ndarray, n: np.ndarray):
-    """Advance (s, t, n) in place to horizon T.  Returns (events, flips)."""
+    """Advance (s, t, n) in place to horizon T.  Returns (events, flips).
+    params["range"] = q > 1 selects the q-th degree neighbourhood."""
     dims = _dims(params)
+    q = int(params.get("range", 1))
+    if q > 1:
+        flips = ctypes.c_uint64(0)
+        ev = lib().oracle_run_range(int(params["dim"]), _p(dims), q,
+                                    float(params.get("J", 1.0)), float(params.get("h", 0.0)),
+                                    float(params["beta"]), float(params.get("rate", 1.0)),
+                                    RULES[params["rule"]], int(params["seed"]), float(T),
+                                    _p(s), _p(t), _p(n), ctypes.byref(flips))
+        if ev < 0:
+            raise ValueError("bad lattice parameters")
+        return int(ev), int(flips.value)
     flips = ctypes.c_uint64(0)
     ev = lib().oracle_run(int(params["dim"]), _p(dims), float(params.get("J", 1.0)),
                           float(params.get("h", 0.0)), float(params["beta"]),

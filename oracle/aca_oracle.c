@@ -357,6 +357,100 @@ OAPI int64_t oracle_run(int dim, const int32_t *L, double J, double h,
 }
 
 /* ------------------------------------------------------------------ */
+/* q-th degree neighbourhoods (Section 3, after Fig. 3.5): the set      */
+/* neighbors^q(c) is built by applying neighbors() q times, i.e. the     */
+/* cells within lattice (L1) distance q of c.  The rule reads the sum    */
+/* of the spins of every cell of that set other than c, so z = |set| - 1 */
+/* takes the place of 2 dim (2D: 2q(q+1)).  Every side must exceed 2q,   */
+/* so that the set has no repeated cell.                                 */
+/* ------------------------------------------------------------------ */
+#define O_MAX_BALL 64
+
+/* Offsets (dx, dy, dz) with 1 <= |dx| + |dy| + |dz| <= q, unused axes 0. */
+static int ball_offsets(int dim, int q, int off[][3])
+{
+    int m = 0;
+    int r1 = q, r2 = dim > 1 ? q : 0, r3 = dim > 2 ? q : 0;
+    for (int dz = -r3; dz <= r3; ++dz)
+        for (int dy = -r2; dy <= r2; ++dy)
+            for (int dx = -r1; dx <= r1; ++dx) {
+                int d = abs(dx) + abs(dy) + abs(dz);
+                if (d < 1 || d > q) continue;
+                if (m >= O_MAX_BALL) return -1;
+                off[m][0] = dx;
+                off[m][1] = dy;
+                off[m][2] = dz;
+                ++m;
+            }
+    return m;
+}
+
+/* thr must hold 2 (z + 1) entries, z = |neighbors^q(c)| - 1; returns that
+ * count, or -1 when the set would exceed O_MAX_BALL cells. */
+OAPI int oracle_thresholds_range(int dim, int q, double J, double h, double beta,
+                                 int rule, uint64_t *thr)
+{
+    int off[O_MAX_BALL][3];
+    if (dim < 1 || dim > 3 || q < 1) return -1;
+    int z = ball_offsets(dim, q, off);
+    if (z < 0) return -1;
+    thresholds(z, J, h, beta, rule, thr);
+    return 2 * (z + 1);
+}
+
+OAPI int64_t oracle_run_range(int dim, const int32_t *L, int q, double J, double h,
+                              double beta, double rate, int rule, uint64_t seed,
+                              double T, int8_t *s, double *t, uint32_t *n,
+                              uint64_t *flips_out)
+{
+    geom g;
+    int off[O_MAX_BALL][3];
+    if (make_geom(dim, L, &g) != 0 || !(rate > 0.0) || isnan(T) || q < 1) return -1;
+    for (int d = 0; d < dim; ++d)
+        if (g.L[d] <= 2 * (int64_t)q) return -1;
+    int z = ball_offsets(dim, q, off);
+    if (z < 0) return -1;
+    uint64_t thr[2 * (O_MAX_BALL + 1)];
+    thresholds(z, J, h, beta, rule, thr);
+
+    uint32_t *heap = (uint32_t *)malloc((size_t)g.n * sizeof(uint32_t));
+    if (!heap) return -1;
+    for (int64_t c = 0; c < g.n; ++c) heap[c] = (uint32_t)c;
+    for (int64_t i = g.n / 2 - 1; i >= 0; --i) sift_down(heap, g.n, i, t);
+
+    int64_t events = 0;
+    uint64_t flips = 0;
+    while (t[heap[0]] < T) {
+        int64_t c = heap[0];
+        int64_t co[3] = {c % g.L[0], (c / g.L[0]) % g.L[1], c / (g.L[0] * g.L[1])};
+        int sum = 0;
+        for (int k = 0; k < z; ++k) {
+            int64_t nb = 0, stride = 1;
+            for (int d = 0; d < 3; ++d) {
+                int64_t x = ((co[d] + off[k][d]) % g.L[d] + g.L[d]) % g.L[d];
+                nb += x * stride;
+                stride *= g.L[d];
+            }
+            sum += s[nb];
+        }
+        uint32_t y[4];
+        draw(seed, n[c], (uint32_t)c, 0u, y);
+        int idx = (sum + z) / 2 + (z + 1) * (s[c] + 1) / 2;
+        if ((uint64_t)y[2] < thr[idx]) {
+            s[c] = (int8_t)(-s[c]);
+            ++flips;
+        }
+        t[c] = t[c] + exp_gap(y[0], y[1], rate);
+        n[c] = n[c] + 1u;
+        ++events;
+        sift_down(heap, g.n, 0, t);
+    }
+    free(heap);
+    if (flips_out) *flips_out = flips;
+    return events;
+}
+
+/* ------------------------------------------------------------------ */
 /* Exported: per-cell arrival clock without any spin dynamics.  The     */
 /* arrival times do not depend on the spins (Section 4), so the first   */
 /* arrival at or after T and the number of arrivals before T follow     */
