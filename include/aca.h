@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define ACA_ABI_VERSION 1u
+#define ACA_ABI_VERSION 2u
 
 typedef int32_t aca_status;
 enum {
@@ -60,7 +60,14 @@ enum { ACA_INIT_RANDOM = 0, ACA_INIT_PLUS = 1, ACA_INIT_MINUS = 2 };
  *  rule    ACA_GLAUBER: flip with 1/(1+exp(beta dE));
  *          ACA_METROPOLIS: flip with min(1, exp(-beta dE))
  *  init    initial spins: iid +/-1 from the seed, all +1, or all -1
- *  seed    64-bit key of the Philox4x32-10 draws */
+ *  seed    64-bit key of the Philox4x32-10 draws
+ *  range   q >= 1: the rule reads the spins of every cell within lattice
+ *          distance q (the q-th degree neighbourhood of Section 3, built by
+ *          applying the nearest-neighbour map q times; z = its size - 1
+ *          replaces 2 dim, e.g. z = 2q(q+1) in 2D).  q > 1 needs every side
+ *          > 2q and q <= 4, 3, 2 in 1, 2, 3 D, and runs on the
+ *          single-lattice path only (not in batches or the server).
+ *          Structures of the size without this field (ABI 1) mean q = 1. */
 typedef struct aca_params {
     uint32_t struct_size;
     int32_t dim;
@@ -68,7 +75,12 @@ typedef struct aca_params {
     double J, h, beta, rate;
     int32_t rule, init;
     uint64_t seed;
+    int32_t range;
+    int32_t pad_;
 } aca_params;
+
+/* Size of aca_params before the range field (still accepted: range 1). */
+#define ACA_PARAMS_SIZE_V1 72u
 
 /* Schedule knobs; they never change results (partition invariance argued
  * for Fig. 3.4), only speed.  struct_size must be sizeof(aca_tuning).
@@ -110,9 +122,10 @@ uint32_t aca_abi_version(void);
 const char *aca_last_error(void);
 
 /* Flip thresholds thr[idx] = floor(p * 2^32) (2^32 when p >= 1), idx =
- * (sum + z)/2 + (z+1)(s+1)/2 with z = 2 dim neighbour slots, for the
- * probability table of the appendix program.  Host only, needs no GPU.
- * out must hold cap >= 2(z+1) entries; *count receives 2(z+1). */
+ * (sum + z)/2 + (z+1)(s+1)/2 with z = 2 dim neighbour slots (or the
+ * q-th degree neighbourhood's size - 1), for the probability table of the
+ * appendix program.  Host only, needs no GPU.  out must hold cap >= 2(z+1)
+ * entries; *count receives 2(z+1). */
 aca_status aca_thresholds(const aca_params *p, uint64_t *out, int32_t cap,
                           int32_t *count);
 

@@ -47,7 +47,11 @@ class Params(ctypes.Structure):
                 ("L", ctypes.c_int32 * 3), ("J", ctypes.c_double), ("h", ctypes.c_double),
                 ("beta", ctypes.c_double), ("rate", ctypes.c_double),
                 ("rule", ctypes.c_int32), ("init", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("range", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+PARAMS_SIZE_V1 = 72     # aca_params without the range field (still accepted)
 
 
 class Tuning(ctypes.Structure):
@@ -166,7 +170,8 @@ def make_params(p: dict) -> Params:
     return Params(ctypes.sizeof(Params), int(p["dim"]), (ctypes.c_int32 * 3)(*L[:3]),
                   float(p.get("J", 1.0)), float(p.get("h", 0.0)), float(p["beta"]),
                   float(p.get("rate", 1.0)), RULES[p.get("rule", "glauber")],
-                  INITS[p.get("init", "random")], int(p["seed"]) & (2**64 - 1))
+                  INITS[p.get("init", "random")], int(p["seed"]) & (2**64 - 1),
+                  int(p.get("range", 1)), 0)
 
 
 def make_tuning(tile=(0, 0, 0), ghost=(-1, -1, -1), max_sweeps=0, block=0) -> Tuning:
@@ -190,9 +195,9 @@ def abi_version() -> int:
 
 def thresholds(p: dict) -> np.ndarray:
     """The library's flip thresholds (host computation, no GPU needed)."""
-    out = np.zeros(14, dtype=np.uint64)
+    out = np.zeros(64, dtype=np.uint64)
     count = ctypes.c_int32(0)
-    _check(load().aca_thresholds(ctypes.byref(make_params(p)), out.ctypes.data, 14,
+    _check(load().aca_thresholds(ctypes.byref(make_params(p)), out.ctypes.data, 64,
                                  ctypes.byref(count)))
     return out[: count.value].copy()
 

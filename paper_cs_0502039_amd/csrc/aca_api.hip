@@ -63,12 +63,33 @@ ScratchLayout scratch_layout(uint64_t n)
 
 bool is_finite(double v) { return std::isfinite(v); }
 
-aca_status check_params(const aca_params *p, uint64_t *n_out)
+int ball_size(int dim, int q)
 {
-    if (!p) return fail(ACA_EINVAL, "params is NULL");
-    if (p->struct_size != sizeof(aca_params))
-        return fail(ACA_EINVAL, "params.struct_size %u != %zu", p->struct_size,
-                    sizeof(aca_params));
+    int m = 0;
+    const int r2 = dim > 1 ? q : 0, r3 = dim > 2 ? q : 0;
+    for (int dz = -r3; dz <= r3; ++dz)
+        for (int dy = -r2; dy <= r2; ++dy)
+            for (int dx = -q; dx <= q; ++dx) {
+                const int d = std::abs(dx) + std::abs(dy) + std::abs(dz);
+                m += (d >= 1 && d <= q) ? 1 : 0;
+            }
+    return m;
+}
+
+aca_status check_params(const aca_params *in, uint64_t *n_out, aca_params *full)
+{
+    if (!in) return fail(ACA_EINVAL, "params is NULL");
+    if (in->struct_size != sizeof(aca_params) && in->struct_size != ACA_PARAMS_SIZE_V1)
+        return fail(ACA_EINVAL, "params.struct_size %u is neither %zu nor %u", in->struct_size,
+                    sizeof(aca_params), ACA_PARAMS_SIZE_V1);
+    aca_params copy;
+    memset(&copy, 0, sizeof copy);
+    memcpy(&copy, in, in->struct_size);
+    if (in->struct_size == ACA_PARAMS_SIZE_V1) copy.range = 1;
+    copy.struct_size = sizeof(aca_params);
+    const aca_params *p = &copy;
+    if (p->range < 1) return fail(ACA_EINVAL, "range %d < 1", p->range);
+    if (p->dim < 1 || p->dim > 3) return fail(ACA_EINVAL, "dim %d not in 1..3", p->dim);
     if (p->dim < 1 || p->dim > 3) return fail(ACA_EINVAL, "dim %d not in 1..3", p->dim);
     uint64_t n = 1;
     for (int d = 0; d < p->dim; ++d) {
@@ -85,7 +106,18 @@ aca_status check_params(const aca_params *p, uint64_t *n_out)
         return fail(ACA_EINVAL, "unknown rule %d", p->rule);
     if (p->init < ACA_INIT_RANDOM || p->init > ACA_INIT_MINUS)
         return fail(ACA_EINVAL, "unknown init %d", p->init);
+    if (p->range > 1) {
+        for (int d = 0; d < p->dim; ++d)
+            if (p->L[d] <= 2 * p->range)
+                return fail(ACA_EINVAL, "L[%d] = %d must exceed twice the range %d", d,
+                            p->L[d], p->range);
+        static const int max_range[4] = {0, 4, 3, 2};
+        if (p->range > max_range[p->dim] || ball_size(p->dim, p->range) > aca::kMaxSlots)
+            return fail(ACA_EINVAL, "range %d exceeds %d in %dD", p->range, max_range[p->dim],
+                        p->dim);
+    }
     if (n_out) *n_out = n;
+    if (full) *full = copy;
     return ACA_OK;
 }
 
@@ -93,7 +125,7 @@ aca_status check_params(const aca_params *p, uint64_t *n_out)
 // entry (sum + z)/2 + (z+1)(s+1)/2 holds floor(p 2^32), 2^32 when p >= 1.
 int build_thresholds(const aca_params *p, uint64_t *thr)
 {
-    const int z = 2 * p->dim;
+    const int z = p->range > 1 ? ball_size(p->dim, p->range) : 2 * p->dim;
     for (int spin = -1; spin <= 1; spin += 2) {
         for (int sum = -z; sum <= z; sum += 2) {
             const double js = p->J * (double)sum;
@@ -117,6 +149,22 @@ int build_thresholds(const aca_params *p, uint64_t *thr)
 // Automatic schedule knobs; every choice gives the same result.
 void auto_tuning(const aca_params &p, aca_tuning *t)
 {
+    if (p.range > 1) {
+        // wider frozen rings: smaller tiles keep two workgroups per CU
+        if (p.dim == 1) {
+            t->tile[0] = 1024; t->ghost[0] = 32;
+            t->max_sweeps = 128; t->block = 256;
+        } else if (p.dim == 2) {
+            t->tile[0] = 56; t->tile[1] = 48;
+            t->ghost[0] = 4; t->ghost[1] = 4;
+            t->max_sweeps = 32; t->block = 512;
+        } else {
+            t->tile[0] = 12; t->tile[1] = 12; t->tile[2] = 8;
+            t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
+            t->max_sweeps = 16; t->block = 512;
+        }
+        return;
+    }
     if (p.dim == 1) {
         t->tile[0] = 8192; t->ghost[0] = 64;
         t->max_sweeps = 512; t->block = 256;
@@ -199,6 +247,12 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
         if (d < p.dim) {
             const int L = p.L[d];
             a.L[d] = L;
+            // a reach beyond the nearest neighbours needs a frozen ring on
+            // every side: cut each direction into at least two tiles (and
+            // keep 1D tiles within LDS)
+            if (p.range > 1 && p.dim == 1 && lat->tun.tile[0] <= 0)
+                t.tile[0] = std::min(t.tile[0], 1024);
+            if (p.range > 1 && t.tile[d] >= L) t.tile[d] = (L + 1) / 2;
             if (t.tile[d] >= L) {
                 a.span[d] = 1; a.tile[d] = L; a.ntiles[d] = 1; a.ghost[d] = 0;
             } else {
@@ -232,8 +286,13 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
                                   lat->device));
     bool spans = false;
     for (int d = 0; d < p.dim; ++d) spans = spans || a.span[d];
+    a.range = p.range;
     plan->fast = !spans && aca::visit_fast_box(p.dim, a) <= 65535 &&
                  aca::visit_fast_lds_bytes(p.dim, a) <= (size_t)dev_lds;
+    if (p.range > 1 && !plan->fast)
+        return fail(ACA_EINVAL, "range %d: the tile region needs %zu B of LDS (device %d B) "
+                    "or more than 65535 cells", p.range, aca::visit_fast_lds_bytes(p.dim, a),
+                    dev_lds);
     if (plan->fast) {
         plan->lds = aca::visit_fast_lds_bytes(p.dim, a);
         return ACA_OK;
@@ -291,13 +350,13 @@ ACA_EXPORT const char *aca_last_error(void) { return g_error.c_str(); }
 ACA_EXPORT aca_status aca_thresholds(const aca_params *p, uint64_t *out, int32_t cap,
                                      int32_t *count)
 {
-    aca_status st = check_params(p, nullptr);
+    aca_params full;
+    aca_status st = check_params(p, nullptr, &full);
     if (st != ACA_OK) return st;
     if (!out) return fail(ACA_EINVAL, "out is NULL");
-    const int need = 2 * (2 * p->dim + 1);
+    uint64_t thr[2 * (aca::kMaxSlots + 1)];
+    const int need = build_thresholds(&full, thr);
     if (cap < need) return fail(ACA_EINVAL, "cap %d < %d entries", cap, need);
-    uint64_t thr[14];
-    build_thresholds(p, thr);
     memcpy(out, thr, sizeof(uint64_t) * need);
     if (count) *count = need;
     return ACA_OK;
@@ -307,7 +366,7 @@ ACA_EXPORT aca_status aca_query(const aca_params *p, uint64_t *n_cells,
                                 uint64_t *scratch_bytes)
 {
     uint64_t n = 0;
-    aca_status st = check_params(p, &n);
+    aca_status st = check_params(p, &n, nullptr);
     if (st != ACA_OK) return st;
     if (n_cells) *n_cells = n;
     if (scratch_bytes) *scratch_bytes = scratch_layout(n).total;
@@ -319,8 +378,10 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
                                  uint64_t scratch_bytes, aca_lattice **out)
 {
     uint64_t n = 0;
-    aca_status st = check_params(p, &n);
+    aca_params full;
+    aca_status st = check_params(p, &n, &full);
     if (st != ACA_OK) return st;
+    p = &full;
     if (!out) return fail(ACA_EINVAL, "out is NULL");
     if (!d_spin || !d_time || !d_count || !d_scratch)
         return fail(ACA_EINVAL, "a device buffer is NULL");

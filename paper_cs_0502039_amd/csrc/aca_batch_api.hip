@@ -323,6 +323,8 @@ ACA_EXPORT aca_status aca_batch_attach(aca_batch *b, aca_lattice *lat, double T)
     if (!b || !lat) return fail(ACA_EINVAL, "NULL argument");
     if (lat->attached) return fail(ACA_ESTATE, "lattice is already a batch member");
     if (!lat->initialized) return fail(ACA_ESTATE, "aca_init (or aca_resume) first");
+    if (lat->p.range > 1)
+        return fail(ACA_EINVAL, "q-th degree neighbourhoods run on the single-lattice path");
     if (lat->device != b->device)
         return fail(ACA_EINVAL, "lattice is on device %d, batch on device %d", lat->device,
                     b->device);

@@ -45,8 +45,14 @@ enum : int {
 };
 
 bool is_finite(double v);
-aca_status check_params(const aca_params *p, uint64_t *n_out);
+// Validates the caller's parameters (either ABI size) and writes a full copy
+// (range 1 for the older size) to *full when full is not NULL.
+aca_status check_params(const aca_params *p, uint64_t *n_out, aca_params *full);
+// Fills the flip table for z neighbours (2 dim, or the q-th degree
+// neighbourhood's size - 1); returns its 2 (z + 1) entries.
 int build_thresholds(const aca_params *p, uint64_t *thr);
+// Cells at lattice distance 1..q (the q-th degree neighbourhood without c).
+int ball_size(int dim, int q);
 
 struct Plan {
     aca::VisitArgs a;
@@ -76,7 +82,7 @@ struct aca_lattice {
     double last_T;
     aca_tuning tun;                 // as requested (0 / -1 = automatic)
     aca_stats stats;
-    uint64_t thr[14];
+    uint64_t thr[2 * (aca::kMaxSlots + 1)];
     int device;
     hipEvent_t ev_start[2], ev_stop[2];
     unsigned long long *host_ctr;   // pinned, mapped, kCounterWords words

@@ -6,6 +6,9 @@
 
 namespace aca {
 
+// Most neighbours a cell's rule may read (q-th degree neighbourhoods).
+constexpr int kMaxSlots = 31;
+
 // Per-launch counters in device scratch (64-bit words).
 enum Counter : int {
     kEvents = 0,        // arrivals applied to owned cells
@@ -49,7 +52,8 @@ struct VisitArgs {
     unsigned long long *host_counters;    // pinned host copy, written by the last block
     unsigned int *done_blocks;            // ticket counter of this slot
     uint8_t *dead;                        // per tile: owned cells final in both snapshots
-    uint64_t thr[14];
+    int32_t range;                        // q of the q-th degree neighbourhood (1: nearest)
+    uint64_t thr[2 * (kMaxSlots + 1)];
     // The advance's horizon T: a cell whose pending time is at or past it is
     // final.  `horizon_bits` above bounds the arrivals this launch may apply;
     // it equals final_bits unless a lag bound is set (then the host sets it
@@ -128,6 +132,8 @@ size_t visit_fast_lds_bytes(int dim, const VisitArgs &a);
 int visit_fast_box(int dim, const VisitArgs &a);
 hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
                              hipStream_t stream);
+// Whether a pitched-box visit exists for this dimension and reach q.
+bool visit_fast_supports(int dim, int q);
 hipError_t set_visit_fast_lds_limit(size_t bytes);
 
 // Caller state (s, t, n) -> working words (flip count 0); adds sum of n to

@@ -122,24 +122,74 @@ struct Stencil {
     }
 };
 
+// The q-th degree neighbourhood without the cell: offsets at lattice
+// distance 1..Q, in a fixed order (Q > 1 only; Q = 1 uses the slots above).
+template <int DIM, int Q>
+struct Ball {
+    static constexpr int count()
+    {
+        int m = 0;
+        for (int dz = -(DIM > 2 ? Q : 0); dz <= (DIM > 2 ? Q : 0); ++dz)
+            for (int dy = -(DIM > 1 ? Q : 0); dy <= (DIM > 1 ? Q : 0); ++dy)
+                for (int dx = -Q; dx <= Q; ++dx) {
+                    const int r = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz);
+                    m += (r >= 1 && r <= Q) ? 1 : 0;
+                }
+        return m;
+    }
+    static constexpr int Z = count();
+    int d[Z][3];
+    constexpr Ball() : d()
+    {
+        int m = 0;
+        for (int dz = -(DIM > 2 ? Q : 0); dz <= (DIM > 2 ? Q : 0); ++dz)
+            for (int dy = -(DIM > 1 ? Q : 0); dy <= (DIM > 1 ? Q : 0); ++dy)
+                for (int dx = -Q; dx <= Q; ++dx) {
+                    const int r = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz);
+                    if (r >= 1 && r <= Q) {
+                        d[m][0] = dx;
+                        d[m][1] = dy;
+                        d[m][2] = dz;
+                        ++m;
+                    }
+                }
+    }
+};
+
 struct FastPlan {
-    size_t thr_off, ctr_off, tab_off, ts_off, n_off, f_off, claim_off, list_off, list_cap,
-        total;
+    size_t thr_off, ctr_off, tmin_off, ball_off, tab_off, ts_off, n_off, f_off, claim_off,
+        list_off, list_cap, total;
 };
 
 // Pitched box: pitch[d] = the largest region box side along d in this launch.
 __host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim)
 {
+    // the frozen ring is as wide as the neighbourhood's reach
+    const int ring = a.range > 1 ? a.range : 1;
     int pitch[3] = {1, 1, 1}, inner = 1;
     for (int d = 0; d < dim; ++d) {
-        pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2;
+        pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2 * ring;
         inner *= a.tile[d] + 2 * a.ghost[d];
     }
     const size_t boxp = (size_t)pitch[0] * pitch[1] * pitch[2];
+    // neighbours the rule reads: 2 dim, or the ball of radius `ring`
+    int z = 2 * dim;
+    if (ring > 1) {
+        z = 0;
+        for (int dz = -(dim > 2 ? ring : 0); dz <= (dim > 2 ? ring : 0); ++dz)
+            for (int dy = -(dim > 1 ? ring : 0); dy <= (dim > 1 ? ring : 0); ++dy)
+                for (int dx = -ring; dx <= ring; ++dx) {
+                    const int r = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz);
+                    z += (r >= 1 && r <= ring) ? 1 : 0;
+                }
+    }
+    const size_t thr_words = 2 * (size_t)(z + 1) > 16 ? 2 * (size_t)(z + 1) : 16;
     FastPlan p;
-    p.thr_off = 0;                                              // uint64 thr[16]
-    p.ctr_off = 128;                                            // int ctr[16]
-    p.tab_off = 192;                                            // uint32 tx, ty, tz
+    p.thr_off = 0;                                              // uint64 thr[2 (z + 1)]
+    p.ctr_off = 8 * thr_words;                                  // int ctr[16]
+    p.tmin_off = p.ctr_off + 64;                                // uint64 least owned time
+    p.ball_off = p.tmin_off + 16;                               // int off[32], step[32]
+    p.tab_off = p.ball_off + (ring > 1 ? 256 : 0);              // uint32 tx, ty, tz
     // uint64 ts[boxp] with a guard of 2*pitch[0] words on both sides: the
     // stencil's two-step loads around a cell on the first or last simulated
     // layer may reach one layer beyond the box (those values are never used)
@@ -165,11 +215,16 @@ struct Snapshots {
 
 // FRAMES: capture output frames as arrivals are applied (a separate
 // instantiation, so the visit without frames carries none of its registers).
-template <int DIM, bool FRAMES = false>
+// Q: the reach of the rule (q-th degree neighbourhood); the frozen ring is Q
+// cells wide.  Q = 1 is the nearest-neighbour visit tuned above; Q > 1 tests
+// and sums over the ball offsets directly.
+template <int DIM, bool FRAMES = false, int Q = 1>
 __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Snapshots io,
                                                     uint32_t tile, unsigned char *lds)
 {
     constexpr int Z = 2 * DIM;
+    constexpr Ball<DIM, (Q > 1 ? Q : 2)> B{};
+    constexpr int ZQ = Q > 1 ? Ball<DIM, (Q > 1 ? Q : 2)>::Z : Z;
     constexpr Stencil<DIM> S{};
     constexpr int K = Stencil<DIM>::K;
     const int tid = threadIdx.x;
@@ -195,16 +250,17 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             const int lo = tc[d] * a.tile[d];
             const int w = min(a.tile[d], a.L[d] - lo);
             rin[d] = w + 2 * a.ghost[d];
-            org[d] = lo - a.ghost[d] - 1;                 // global coordinate of box 0
-            olo[d] = a.ghost[d] + 1;                      // own cells, box coordinates
-            ohi[d] = a.ghost[d] + 1 + w;
-            pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2;
+            org[d] = lo - a.ghost[d] - Q;                 // global coordinate of box 0
+            olo[d] = a.ghost[d] + Q;                      // own cells, box coordinates
+            ohi[d] = a.ghost[d] + Q + w;
+            pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2 * Q;
         } else {
             side[d] = 1; rin[d] = 1; org[d] = 0; olo[d] = 0; ohi[d] = 1; pitch[d] = 1;
         }
     }
     const int P1 = pitch[0], P12 = pitch[0] * pitch[1];
-    const int rb[3] = {DIM > 0 ? rin[0] + 2 : 1, DIM > 1 ? rin[1] + 2 : 1, DIM > 2 ? rin[2] + 2 : 1};
+    const int rb[3] = {DIM > 0 ? rin[0] + 2 * Q : 1, DIM > 1 ? rin[1] + 2 * Q : 1,
+                       DIM > 2 ? rin[2] + 2 * Q : 1};
     const int inner = rin[0] * rin[1] * rin[2];
     const uint32_t magic1 = 0xFFFFFFFFu / (uint32_t)P1 + 1u;            // P1 >= 3
     const uint32_t magic2 = pitch[1] > 1 ? 0xFFFFFFFFu / (uint32_t)pitch[1] + 1u : 0u;
@@ -225,8 +281,21 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     int *takes = ctr + 3;    // [3..5] take positions, rotating over rounds
 
     // ---- tables: global offsets of box rows/columns/planes; clear claims
-    if (tid < 2 * (Z + 1)) thr[tid] = a.thr[tid];
-    if (tid == 15) thr[15] = ~0ull;     // least owned pending time (lag bound)
+    uint64_t *tmin_slot = reinterpret_cast<uint64_t *>(lds + plan.tmin_off);
+    // Q > 1: box offset and packed coordinate step of every ball entry
+    int *ball_box = reinterpret_cast<int *>(lds + plan.ball_off);
+    int *ball_step = ball_box + 32;
+    if constexpr (Q > 1) {
+#pragma unroll
+        for (int k = 0; k < ZQ; ++k)
+            if (tid == k) {
+                ball_box[k] = B.d[k][0] + P1 * B.d[k][1] + P12 * B.d[k][2];
+                ball_step[k] = (B.d[k][0] + 16) | ((B.d[k][1] + 16) << 8) |
+                               ((B.d[k][2] + 16) << 16);
+            }
+    }
+    if (tid < 2 * (ZQ + 1)) thr[tid] = a.thr[tid];
+    if (tid == 0) *tmin_slot = ~0ull;   // least owned pending time (lag bound)
     if (tid < 16) ctr[tid] = 0;
     for (int j = tid; j < rb[0]; j += nthreads) tx[j] = (uint32_t)wrap_into(org[0] + j, side[0]);
     for (int j = tid; j < rb[1]; j += nthreads)
@@ -260,7 +329,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     auto is_inner = [&](const int *q) {
         bool in = true;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) in = in && q[d] >= 1 && q[d] <= rin[d];
+        for (int d = 0; d < DIM; ++d) in = in && q[d] >= Q && q[d] < Q + rin[d];
         return in;
     };
     constexpr int U = 4;    // cells per thread in flight in the load and merge loops
@@ -305,10 +374,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             }
         }
     }
-    if (a.track_tmin && tmin_own != ~0ull) atomicMin(&thr[15], tmin_own);
+    if (a.track_tmin && tmin_own != ~0ull) atomicMin(tmin_slot, tmin_own);
     const int own_due = __syncthreads_or(due ? 1 : 0);
-    if (a.track_tmin && tid == 0 && thr[15] != ~0ull)
-        atomicMin(&a.counters[kTminBits], (unsigned long long)thr[15]);
+    if (a.track_tmin && tid == 0 && *tmin_slot != ~0ull)
+        atomicMin(&a.counters[kTminBits], (unsigned long long)*tmin_slot);
 
     // arrivals before this launch's horizon may be applied; cells at or past
     // the advance's horizon are final
@@ -341,6 +410,38 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         return en;
     };
 
+    // ---- Q > 1: the rule's ball, read entry by entry
+    auto gidx_at = [&](const int *qq) { return tx[qq[0]] + ty[qq[1]] + tz[qq[2]]; };
+    auto step_of = [&](int k, int *qq) {
+        const int st = ball_step[k];
+        qq[0] += (st & 0xFF) - 16;
+        qq[1] += ((st >> 8) & 0xFF) - 16;
+        qq[2] += ((st >> 16) & 0xFF) - 16;
+    };
+    // enabled when before the horizon and before every ball cell; `tie` when
+    // the least ball time equals the cell's (decided by exact_q)
+    auto enabled_q = [&](int xb, uint64_t wx, bool &tie) {
+        const double tc = time_of(wx);
+        double tmin = time_of(ldw(&ts[xb + ball_box[0]]));
+        for (int k = 1; k < ZQ; ++k) tmin = __builtin_fmin(tmin, time_of(ldw(&ts[xb + ball_box[k]])));
+        const bool live = tc < horizon_t;
+        tie = live && tc == tmin;
+        return live && tc < tmin;
+    };
+    // the (time, global index) order against every ball cell
+    auto exact_q = [&](int xb, const int *qx, uint64_t wx) {
+        const uint64_t tcb = wx & kMask;
+        const uint32_t gx = gidx_at(qx);
+        bool en = tcb < horizon;
+        for (int k = 0; k < ZQ; ++k) {
+            int qy[3] = {qx[0], qx[1], qx[2]};
+            step_of(k, qy);
+            const uint64_t tyb = ldw(&ts[xb + ball_box[k]]) & kMask;
+            en = en && (tcb < tyb || (tcb == tyb && gx < gidx_at(qy)));
+        }
+        return en;
+    };
+
     int rounds = 0;
     if (own_due) {
     // ---- initial scan: every enabled simulated cell, claimed, into list 0
@@ -350,7 +451,14 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         const int bi = j;
         int q[3];
         decode(min(j, boxp - 1), q);
-        if (j < boxp && is_inner(q)) {
+        if (Q > 1 && j < boxp && is_inner(q)) {
+            const uint64_t wc = ldw(&ts[bi]);
+            bool tie = false;
+            en = enabled_q(bi, wc, tie);
+            if (tie) en = exact_q(bi, q, wc);
+            ++my_checks;
+            if (en) atomicOr(&claim[bi >> 5], 1u << (bi & 31));
+        } else if (Q == 1 && j < boxp && is_inner(q)) {
             const uint64_t wc = ldw(&ts[bi]);
             uint64_t tn[Z];
             double tmin = time_of(ldw(&ts[bi + off(1)]));
@@ -399,6 +507,76 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             start = __shfl(start, 0, 64);
             if (start >= sz) break;
             const bool active = lane < sz - start;
+            if constexpr (Q > 1) {
+                // ---- one arrival per lane, rule over the ball
+                int bi = 0, q[3] = {0, 0, 0};
+                if (active) {
+                    bi = lcur[start + lane];
+                    decode(bi, q);
+                    atomicAnd(&claim[bi >> 5], ~(1u << (bi & 31)));
+                    const uint64_t w0 = ldw(&ts[bi]);
+                    int sum = 0;
+                    for (int k = 0; k < ZQ; ++k) sum += (ldw(&ts[bi + ball_box[k]]) >> 63) ? -1 : 1;
+                    const uint32_t kn = nl[bi];
+                    const uint32_t gidx = gidx_at(q);
+                    const Draw y = philox4x32_10(kn, gidx, 0u, 0u, a.key_lo, a.key_hi);
+                    const int idx = (sum + ZQ) / 2 + (ZQ + 1) * ((w0 >> 63) ? 0 : 1);
+                    const bool flip = (uint64_t)y.w2 < thr[idx];
+                    const double tnow = __longlong_as_double((long long)(w0 & kMask));
+                    const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
+                    const uint64_t wnew = (uint64_t)__double_as_longlong(tnext) |
+                                          ((w0 & kSign) ^ (flip ? kSign : 0ull));
+                    if (FRAMES)
+                        capture_frames(a.frames, a.frame_dt, a.frame_k0, a.nframes, a.n_cells,
+                                       gidx, tnow, __builtin_fmin(tnext, final_t),
+                                       (wnew >> 63) ? (int8_t)-1 : (int8_t)1);
+                    nl[bi] = kn + 1u;
+                    fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    stw(&ts[bi], wnew);
+                    if (is_own(q)) {
+                        ++my_events;
+                        my_flips += flip ? 1u : 0u;
+                    } else {
+                        ++my_ghost;
+                    }
+                }
+                // re-test the applied cell and every cell of its ball (they
+                // hold it in theirs) once this lane's arrival is published
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                const uint64_t below = (1ull << lane) - 1ull;
+                for (int k = -1; k < ZQ; ++k) {
+                    int qx[3] = {q[0], q[1], q[2]};
+                    int xb = bi;
+                    if (k >= 0) {
+                        step_of(k, qx);
+                        xb += ball_box[k];
+                    }
+                    const bool inside = active && is_inner(qx);
+                    bool want = false, tie = false;
+                    uint64_t wx = 0;
+                    if (inside) {
+                        wx = ldw(&ts[xb]);
+                        want = enabled_q(xb, wx, tie);
+                        ++my_checks;
+                    }
+                    if (__ballot(tie)) {
+                        if (tie) want = exact_q(xb, qx, wx);
+                    }
+                    if (want) {
+                        const uint32_t bit = 1u << (xb & 31);
+                        want = (atomicOr(&claim[xb >> 5], bit) & bit) == 0u;
+                    }
+                    const uint64_t mk = __ballot(want);
+                    if (mk) {
+                        int b0 = 0;
+                        if (lane == 0) b0 = atomicAdd(next_size, (int)__popcll(mk));
+                        b0 = __shfl(b0, 0, 64);
+                        if (want) lnext[b0 + (int)__popcll(mk & below)] = (uint16_t)xb;
+                    }
+                }
+                continue;
+            }
             int bi = 0, q[3] = {0, 0, 0};
             uint64_t W[K];
             if (active) {

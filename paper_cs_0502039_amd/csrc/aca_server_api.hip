@@ -243,8 +243,14 @@ ACA_EXPORT aca_status aca_server_submit(aca_server *srv, const aca_params *p, do
                                         uint64_t *job)
 {
     if (!srv || !p) return fail(ACA_EINVAL, "NULL argument");
+    aca_params full;
+    aca_status st = check_params(p, nullptr, &full);
+    if (st != ACA_OK) return st;
+    if (full.range > 1)
+        return fail(ACA_EINVAL, "q-th degree neighbourhoods run on the single-lattice path");
+    p = &full;
     JobLayout l;
-    aca_status st = job_layout(p, &l);
+    st = job_layout(p, &l);
     if (st != ACA_OK) return st;
     if (!is_finite(T) || T <= 0.0) return fail(ACA_EINVAL, "horizon must be finite and > 0");
     if (l.total > srv->alloc.size())

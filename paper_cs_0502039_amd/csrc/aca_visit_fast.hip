@@ -12,14 +12,14 @@
 namespace aca {
 namespace {
 
-template <int DIM, bool FRAMES>
+template <int DIM, bool FRAMES, int Q>
 __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                                       (unsigned)a.ntiles[2];
     const region::Snapshots io{a.key_in, a.time_in, a.key_out, a.time_out};
-    const region::RegionTally r = region::visit_region<DIM, FRAMES>(a, io, blockIdx.x, lds);
+    const region::RegionTally r = region::visit_region<DIM, FRAMES, Q>(a, io, blockIdx.x, lds);
     if (threadIdx.x == 0) {
         if (!r.skipped) {
             unsigned long long *gc = a.counters;
@@ -37,62 +37,82 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
     }
 }
 
+// Every (dimension, frames, reach) instantiation: reach 1..4 in 1D, 1..3 in
+// 2D, 1..2 in 3D.
+template <int DIM, bool FRAMES, int Q>
+const void *fast_fn()
+{
+    return (const void *)visit_fast_kernel<DIM, FRAMES, Q>;
+}
+
+template <bool FRAMES>
+const void *fast_fn_for(int dim, int q)
+{
+    if (dim == 1) {
+        switch (q) {
+        case 1: return fast_fn<1, FRAMES, 1>();
+        case 2: return fast_fn<1, FRAMES, 2>();
+        case 3: return fast_fn<1, FRAMES, 3>();
+        case 4: return fast_fn<1, FRAMES, 4>();
+        default: return nullptr;
+        }
+    }
+    if (dim == 2) {
+        switch (q) {
+        case 1: return fast_fn<2, FRAMES, 1>();
+        case 2: return fast_fn<2, FRAMES, 2>();
+        case 3: return fast_fn<2, FRAMES, 3>();
+        default: return nullptr;
+        }
+    }
+    switch (q) {
+    case 1: return fast_fn<3, FRAMES, 1>();
+    case 2: return fast_fn<3, FRAMES, 2>();
+    default: return nullptr;
+    }
+}
+
+const void *fast_kernel(int dim, int q, bool frames)
+{
+    return frames ? fast_fn_for<true>(dim, q) : fast_fn_for<false>(dim, q);
+}
+
 }  // namespace
 
 size_t visit_fast_lds_bytes(int dim, const VisitArgs &a) { return region::fast_plan(a, dim).total; }
 
 int visit_fast_box(int dim, const VisitArgs &a)
 {
+    const int ring = a.range > 1 ? a.range : 1;
     int box = 1;
-    for (int d = 0; d < dim; ++d) box *= a.tile[d] + 2 * a.ghost[d] + 2;
+    for (int d = 0; d < dim; ++d) box *= a.tile[d] + 2 * a.ghost[d] + 2 * ring;
     return box;
 }
 
-template <bool FRAMES>
-void launch_fast(int dim, const VisitArgs &a, unsigned tiles, int block, size_t lds,
-                 hipStream_t stream)
-{
-    switch (dim) {
-    case 1:
-        hipLaunchKernelGGL((visit_fast_kernel<1, FRAMES>), dim3(tiles), dim3(block), lds,
-                           stream, a);
-        break;
-    case 2:
-        hipLaunchKernelGGL((visit_fast_kernel<2, FRAMES>), dim3(tiles), dim3(block), lds,
-                           stream, a);
-        break;
-    default:
-        hipLaunchKernelGGL((visit_fast_kernel<3, FRAMES>), dim3(tiles), dim3(block), lds,
-                           stream, a);
-        break;
-    }
-}
+bool visit_fast_supports(int dim, int q) { return fast_kernel(dim, q, false) != nullptr; }
 
 hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
                              hipStream_t stream)
 {
     const unsigned tiles = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                            (unsigned)a.ntiles[2];
-    if (a.frames)
-        launch_fast<true>(dim, a, tiles, block, lds, stream);
-    else
-        launch_fast<false>(dim, a, tiles, block, lds, stream);
-    return hipGetLastError();
+    const void *fn = fast_kernel(dim, a.range > 1 ? a.range : 1, a.frames != nullptr);
+    if (!fn) return hipErrorInvalidValue;
+    void *args[] = {const_cast<VisitArgs *>(&a)};
+    return hipLaunchKernel(fn, dim3(tiles), dim3(block), args, lds, stream);
 }
 
 hipError_t set_visit_fast_lds_limit(size_t bytes)
 {
-    const void *fns[6] = {(const void *)visit_fast_kernel<1, false>,
-                          (const void *)visit_fast_kernel<2, false>,
-                          (const void *)visit_fast_kernel<3, false>,
-                          (const void *)visit_fast_kernel<1, true>,
-                          (const void *)visit_fast_kernel<2, true>,
-                          (const void *)visit_fast_kernel<3, true>};
-    for (const void *f : fns) {
-        const hipError_t e =
-            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
+    for (int dim = 1; dim <= 3; ++dim)
+        for (int q = 1; q <= 4; ++q)
+            for (int fr = 0; fr < 2; ++fr) {
+                const void *f = fast_kernel(dim, q, fr != 0);
+                if (!f) continue;
+                const hipError_t e =
+                    hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                if (e != hipSuccess) return e;
+            }
     return hipSuccess;
 }
 

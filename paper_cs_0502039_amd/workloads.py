@@ -87,6 +87,15 @@ def served_stream(count: int = 400, rate_jobs_per_s: float = 1.0) -> list[dict]:
     return jobs
 
 
+def square_1024_range(q: int = 2) -> dict:
+    """A 1024x1024 torus whose rule reads the q-th degree neighbourhood
+    (every cell within lattice distance q: 12 neighbours for q = 2), beta 0.12
+    (above the ordering temperature of that coupling range), T = 50."""
+    p = lattice(2, (1024, 1024), 0.12 if q == 2 else 0.06, "glauber", seed=8, T=50.0)
+    p["range"] = q
+    return p
+
+
 def small_cases() -> list[dict]:
     """Small lattices for element-by-element parity: several tiles, ragged edges,
     every dimension, both rules, odd sides, side 2, fields and couplings of both

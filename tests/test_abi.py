@@ -37,7 +37,41 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert aca.abi_version() == 1
+    assert aca.abi_version() == 2
+
+
+def test_params_of_the_first_abi_size_accepted():
+    """aca_params without the trailing range field (ABI 1) means range 1."""
+    lib = aca.load()
+    p = aca.make_params(workloads.lattice(2, (8, 8), 0.3))
+    p.struct_size = aca.PARAMS_SIZE_V1
+    p.range = 7                          # beyond the declared size: never read
+    n = ctypes.c_uint64()
+    assert lib.aca_query(ctypes.byref(p), ctypes.byref(n), None) == aca.ACA_OK
+    out = np.zeros(64, dtype=np.uint64)
+    cnt = ctypes.c_int32()
+    assert lib.aca_thresholds(ctypes.byref(p), out.ctypes.data, 64, ctypes.byref(cnt)) == 0
+    assert cnt.value == 10
+
+
+@pytest.mark.parametrize("dim,q", [(1, 2), (1, 4), (2, 2), (2, 3), (3, 2)])
+def test_range_thresholds_equal_oracle(dim, q):
+    L = [2 * q + 1 + d for d in range(dim)]
+    for rule in ("glauber", "metropolis"):
+        p = workloads.lattice(dim, L, 0.37, rule, h=0.15, J=0.8)
+        p["range"] = q
+        assert np.array_equal(aca.thresholds(p), oracle.thresholds(dim, 0.8, 0.15, 0.37,
+                                                                   rule, q))
+
+
+@pytest.mark.parametrize("dim,L,q", [(2, (9, 9), 0), (2, (9, 9), 4), (3, (9, 9, 9), 3),
+                                     (1, (40,), 5), (2, (4, 9), 2), (1, (6,), 3)])
+def test_invalid_ranges_rejected(dim, L, q):
+    p = workloads.lattice(dim, L, 0.3)
+    p["range"] = q
+    with pytest.raises(aca.AcaError) as e:
+        aca.query(p)
+    assert e.value.code == aca.ACA_EINVAL
 
 
 @pytest.mark.parametrize("params", workloads.small_cases()

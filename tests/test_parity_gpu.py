@@ -335,3 +335,75 @@ def test_frames_and_lag_argument_errors(torch):
     with pytest.raises(aca.AcaError):
         lat.advance_frames(1.0, 0.5, frames, -1)
     lat.close()
+
+
+# ------------------------------------------------------------ q-th degree neighbourhoods
+
+def _with_range(p, q):
+    p = dict(p)
+    p["range"] = q
+    return p
+
+
+RANGE_CASES = [
+    _with_range(workloads.lattice(2, (40, 33), 0.2, seed=71, T=6.0), 2),
+    _with_range(workloads.lattice(2, (200, 131), 0.12, "metropolis", h=0.1, seed=72, T=4.0), 2),
+    _with_range(workloads.lattice(2, (97, 88), 0.08, seed=73, T=3.0), 3),
+    _with_range(workloads.lattice(3, (20, 18, 17), 0.06, "metropolis", h=-0.1, init="plus",
+                                  seed=74, T=2.0), 2),
+    _with_range(workloads.lattice(1, (301,), 0.3, seed=75, T=10.0), 4),
+    _with_range(workloads.lattice(2, (9, 11), 0.0, "metropolis", seed=76, T=5.0), 2),
+]
+
+
+@pytest.mark.parametrize("params", RANGE_CASES,
+                         ids=lambda p: f"{p['dim']}d-{p['L']}-q{p['range']}")
+def test_range_matches_oracle(torch, params):
+    s, t, n, st = aca.simulate(params)
+    so, to, no, ev, fl = oracle.simulate(params, params["T"])
+    assert_same_state((s, t, n), (so, to, no), f"range {params['range']}")
+    assert st["events"] == ev and st["flips"] == fl
+
+
+@pytest.mark.parametrize("tuning", [dict(tile=(7, 5, 3), ghost=(2, 1, 1), max_sweeps=3),
+                                    dict(tile=(16, 16, 4), ghost=(0, 0, 0), max_sweeps=1),
+                                    dict(tile=(33, 9, 9), ghost=(5, 3, 2), max_sweeps=200)])
+@pytest.mark.parametrize("params", RANGE_CASES[:4],
+                         ids=lambda p: f"{p['dim']}d-{p['L']}-q{p['range']}")
+def test_range_tiling_does_not_change_results(torch, params, tuning):
+    s, t, n, _ = aca.simulate(params, tuning=tuning)
+    so, to, no, _, _ = oracle.simulate(params, params["T"])
+    assert_same_state((s, t, n), (so, to, no), f"range tiling {tuning}")
+
+
+def test_range_with_frames_lag_and_chunks(torch):
+    params = RANGE_CASES[1]
+    lat = aca.Lattice(params).init()
+    lat.set_lag(0.4)
+    frames = torch.zeros((12, lat.n), dtype=torch.int8, device="cuda")
+    lat.advance_frames(params["T"] / 2, 0.5, frames, 1)
+    lat.advance_frames(params["T"], 0.5, frames, 1)
+    s, t, c = oracle.init(params)
+    want = oracle.frames(params, 0.0, params["T"] / 2, 0.5, 1, 12, s, t, c)
+    want.update(oracle.frames(params, params["T"] / 2, params["T"], 0.5, 1, 12, s, t, c))
+    got = frames.cpu().numpy()
+    for k, img in want.items():
+        assert np.array_equal(got[k - 1], img), f"frame {k}"
+    assert_same_state(lat.read(), (s, t, c), "final")
+    lat.close()
+
+
+def test_range_not_accepted_by_batches_or_server(torch):
+    p = RANGE_CASES[0]
+    lat = aca.Lattice(p).init()
+    batch = aca.Batch(2)
+    with pytest.raises(aca.AcaError) as e:
+        batch.attach(lat, 1.0)
+    assert e.value.code == aca.ACA_EINVAL
+    server = aca.Server(1 << 24, max_jobs=2)
+    with pytest.raises(aca.AcaError) as e:
+        server.submit(p)
+    assert e.value.code == aca.ACA_EINVAL
+    server.close()
+    batch.close()
+    lat.close()
