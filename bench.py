@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -290,6 +292,49 @@ def bench_lag(lags, T: float = 50.0, frame_dt: float = 5.0) -> dict:
                        "ms_without": base}}
 
 
+def bench_range(qs=(1, 2, 3), steps: int = 3, cpu_sample_T: float = 0.5) -> dict:
+    """q-th degree neighbourhoods on a 1024^2 torus to T = 50: spin-updates per
+    second per reach, each run checked against the one-shot result of another
+    tiling, and the oracle on one host core for reach 2 (bounded sample)."""
+    import torch
+    from paper_cs_0502039_amd import aca, workloads
+    rows = []
+    for q in qs:
+        params = workloads.square_1024_range(q) if q > 1 else dict(
+            workloads.square_1024_range(2), range=1, beta=0.4)
+        lat = aca.Lattice(params)
+        lat.init().advance(params["T"])
+        ref = lat.read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lat.init().advance(params["T"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = lat.stats()
+        other = aca.Lattice(params, tuning=dict(tile=(40, 40), ghost=(2, 2), max_sweeps=20))
+        other.init().advance(params["T"])
+        same = all(np.array_equal(x, y) for x, y in zip(ref, other.read()))
+        other.close()
+        rows.append({"range": q, "neighbours": len(aca.thresholds(params)) // 2 - 1,
+                     "beta": params["beta"], "ms": dt * 1e3,
+                     "spin_updates_per_s": st["events"] / dt, "launches": st["launches"],
+                     "tuning": lat.tuning(), "tilings_agree": same})
+        log(f"range {q}: {dt * 1e3:.1f} ms, {st['events'] / dt:.3e} spin-updates/s")
+        lat.close()
+    out = {"workload": "square_1024_range", "T": 50.0, "rows": rows}
+    if cpu_sample_T > 0:
+        import oracle
+        params = workloads.square_1024_range(2)
+        s, t, n = oracle.init(params)
+        t0 = time.time()
+        ev, _ = oracle.run(params, cpu_sample_T, s, t, n)
+        out["cpu_baseline"] = {"value": ev / (time.time() - t0), "unit": "spin-updates/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"1024^2, range 2, initial state to T={cpu_sample_T}"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,7 +354,8 @@ def main() -> int:
                     help="keep the automatic schedules instead of tuning on the workload")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--only", choices=("single", "batched", "served", "lag"), default=None)
+    ap.add_argument("--only", choices=("single", "batched", "served", "lag", "range"),
+                    default=None)
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-arena-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=512)
@@ -332,6 +378,9 @@ def main() -> int:
     if args.only == "lag":
         print(json.dumps({"lag": bench_lag([0.0, 16.0, 8.0, 4.0, 2.0, 1.0, 0.5, 0.3])}),
               flush=True)
+        return 0
+    if args.only == "range":
+        print(json.dumps({"range": bench_range()}), flush=True)
         return 0
     if args.only == "served":
         print(json.dumps({"served": bench_served(args.serve_arena_gib, args.serve_slots,
