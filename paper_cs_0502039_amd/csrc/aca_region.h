@@ -483,7 +483,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         if (m) {
             int b0 = 0;
             if (lane == 0) b0 = atomicAdd(&sizes[0], (int)__popcll(m));
-            b0 = __shfl(b0, 0, 64);
+            b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
             if (en) lists[b0 + (int)__popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)bi;
         }
     }
@@ -504,7 +504,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         for (;;) {
             int start = 0;
             if (lane == 0) start = atomicAdd(&takes[rnd % 3], 64);
-            start = __shfl(start, 0, 64);
+            start = __builtin_amdgcn_readfirstlane(start);  // lane 0 is active
             if (start >= sz) break;
             const bool active = lane < sz - start;
             if constexpr (Q > 1) {
@@ -571,7 +571,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                     if (mk) {
                         int b0 = 0;
                         if (lane == 0) b0 = atomicAdd(next_size, (int)__popcll(mk));
-                        b0 = __shfl(b0, 0, 64);
+                        b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
                         if (want) lnext[b0 + (int)__popcll(mk & below)] = (uint16_t)xb;
                     }
                 }
@@ -698,7 +698,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             if (total) {
                 int b0 = 0;
                 if (lane == 0) b0 = atomicAdd(next_size, total);
-                b0 = __shfl(b0, 0, 64);
+                b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
                 const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
                 for (int s = 0; s <= Z; ++s) {
