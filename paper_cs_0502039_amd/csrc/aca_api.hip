@@ -173,9 +173,11 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->ghost[0] = 4; t->ghost[1] = 4;
         t->max_sweeps = 32; t->block = 512;
     } else {
-        t->tile[0] = 16; t->tile[1] = 16; t->tile[2] = 8;
+        // one 20x20x12 region fills most of a CU's LDS: 1024 threads keep
+        // sixteen wavefronts per CU
+        t->tile[0] = 20; t->tile[1] = 20; t->tile[2] = 12;
         t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
-        t->max_sweeps = 16; t->block = 512;
+        t->max_sweeps = 16; t->block = 1024;
     }
 }
 
@@ -188,9 +190,11 @@ int tune_candidates(int dim, aca_tuning *out)
                                 {64, 48, 3, 32, 0}, {48, 48, 4, 32, 0}, {96, 40, 4, 32, 0},
                                 {64, 64, 3, 32, 0}, {32, 32, 2, 16, 0}, {64, 56, 2, 16, 0},
                                 {56, 56, 4, 32, 0}};
-    static const int c3[][5] = {{16, 16, 8, 1, 16}, {16, 16, 16, 1, 16}, {16, 16, 8, 1, 12},
-                                {16, 16, 8, 1, 24}, {16, 8, 8, 1, 16}, {8, 8, 8, 1, 8},
-                                {16, 16, 16, 1, 12}, {24, 16, 8, 1, 16}};
+    // tile sides, ghost, rounds, threads
+    static const int c3[][6] = {{20, 20, 12, 1, 16, 1024}, {16, 16, 8, 1, 16, 512},
+                                {16, 16, 16, 1, 16, 1024}, {20, 20, 12, 1, 12, 1024},
+                                {20, 20, 12, 1, 24, 1024}, {16, 16, 8, 1, 12, 512},
+                                {20, 16, 12, 1, 16, 1024}, {8, 8, 8, 1, 8, 512}};
     int n = 0;
     auto base = [&]() -> aca_tuning & {
         aca_tuning &t = out[n++];
@@ -217,6 +221,7 @@ int tune_candidates(int dim, aca_tuning *out)
             t.tile[0] = c[0]; t.tile[1] = c[1]; t.tile[2] = c[2];
             t.ghost[0] = t.ghost[1] = t.ghost[2] = c[3];
             t.max_sweeps = c[4];
+            t.block = c[5];
         }
     }
     return n;

@@ -257,9 +257,12 @@ __device__ void close_epoch(BatchState &st, uint32_t epoch, BatchGlobal *g)
 }
 
 // DIM = 1, 2 or 3 when every member has that dimension, 0 for a mix (the
-// dimension is then read per item).  Two blocks must fit a compute unit.
-template <int DIM>
-__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4)))
+// dimension is then read per item).  WAVES = 4 wavefronts per SIMD when two
+// workgroups fit a compute unit's LDS (at most 128 registers per lane), 2
+// when the regions are so large that only one does (then up to 256 registers
+// per lane cost no occupancy).
+template <int DIM, int WAVES>
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(WAVES)))
 batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *order,
                    uint32_t norder, BatchGlobal *g, unsigned long long wait_limit)
 {
@@ -319,25 +322,37 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
 
 size_t batch_lds_bytes(int dim, const VisitArgs &a) { return region::fast_plan(a, dim).total; }
 
-int batch_block_size() { return kBatchBlock; }
+namespace {
+// Regions above half of a compute unit's LDS leave room for one workgroup.
+int waves_for(size_t lds) { return lds > 80 * 1024 ? 2 : 4; }
+}  // namespace
 
-const void *batch_visit_fn(int dim)
+int batch_block_size(size_t) { return kBatchBlock; }
+
+template <int WAVES>
+const void *batch_visit_fn_w(int dim)
 {
     switch (dim) {
-    case 1: return (const void *)batch_visit_kernel<1>;
-    case 2: return (const void *)batch_visit_kernel<2>;
-    case 3: return (const void *)batch_visit_kernel<3>;
-    default: return (const void *)batch_visit_kernel<0>;
+    case 1: return (const void *)batch_visit_kernel<1, WAVES>;
+    case 2: return (const void *)batch_visit_kernel<2, WAVES>;
+    case 3: return (const void *)batch_visit_kernel<3, WAVES>;
+    default: return (const void *)batch_visit_kernel<0, WAVES>;
     }
+}
+
+const void *batch_visit_fn(int dim, size_t lds)
+{
+    return waves_for(lds) == 2 ? batch_visit_fn_w<2>(dim) : batch_visit_fn_w<4>(dim);
 }
 
 hipError_t set_batch_lds_limit(size_t bytes)
 {
-    for (int d = 0; d <= 3; ++d) {
-        const hipError_t e = hipFuncSetAttribute(
-            batch_visit_fn(d), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
+    for (int d = 0; d <= 3; ++d)
+        for (size_t l : {(size_t)0, (size_t)160 * 1024}) {
+            const hipError_t e = hipFuncSetAttribute(
+                batch_visit_fn(d, l), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 
@@ -345,7 +360,7 @@ hipError_t batch_max_blocks(int dim, size_t lds, int *blocks)
 {
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, batch_visit_fn(dim), kBatchBlock, lds);
+        &per_cu, batch_visit_fn(dim, lds), kBatchBlock, lds);
     if (e != hipSuccess) return e;
     e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -381,25 +396,10 @@ hipError_t launch_batch_visit(int dim, const BatchSlot *slots, BatchState *state
                               unsigned long long wait_limit_ticks, int blocks, size_t lds,
                               hipStream_t stream)
 {
-    switch (dim) {
-    case 1:
-        hipLaunchKernelGGL(batch_visit_kernel<1>, dim3(blocks), dim3(kBatchBlock), lds,
-                           stream, slots, state, order, norder, g, wait_limit_ticks);
-        break;
-    case 2:
-        hipLaunchKernelGGL(batch_visit_kernel<2>, dim3(blocks), dim3(kBatchBlock), lds,
-                           stream, slots, state, order, norder, g, wait_limit_ticks);
-        break;
-    case 3:
-        hipLaunchKernelGGL(batch_visit_kernel<3>, dim3(blocks), dim3(kBatchBlock), lds,
-                           stream, slots, state, order, norder, g, wait_limit_ticks);
-        break;
-    default:
-        hipLaunchKernelGGL(batch_visit_kernel<0>, dim3(blocks), dim3(kBatchBlock), lds,
-                           stream, slots, state, order, norder, g, wait_limit_ticks);
-        break;
-    }
-    return hipGetLastError();
+    void *args[] = {(void *)&slots, (void *)&state, (void *)&order, (void *)&norder,
+                    (void *)&g, (void *)&wait_limit_ticks};
+    return hipLaunchKernel(batch_visit_fn(dim, lds), dim3(blocks), dim3(kBatchBlock), args,
+                           lds, stream);
 }
 
 hipError_t launch_batch_unpack(const BatchSlot *slots, BatchState *state,

@@ -105,20 +105,15 @@ struct aca_batch {
 
 namespace {
 
-// Automatic knobs of batch members.  Members are often small, and a batch
-// mixes dimensions in one launch, so 3D members take cubic 16^3 tiles (fewer
-// tiles per small lattice than the single-lattice 16x16x8 choice).
+// Automatic knobs of batch members: those of a single lattice (the
+// persistent kernel picks its own threads per workgroup).
 void batch_auto_tuning(int dim, aca_tuning *t)
 {
     aca_params p;
     memset(&p, 0, sizeof p);
     p.dim = dim;
+    p.range = 1;
     auto_tuning(p, t);
-    if (dim == 3) {
-        t->tile[0] = t->tile[1] = t->tile[2] = 16;
-        t->ghost[0] = t->ghost[1] = t->ghost[2] = 1;
-        t->max_sweeps = 16;
-    }
 }
 
 // Tile plan of a batch member: at least two tiles along every direction, so
@@ -304,7 +299,7 @@ ACA_EXPORT aca_status aca_batch_get_tuning(const aca_batch *b, int32_t dim, aca_
     }
     if (u.max_sweeps > 0) t.max_sweeps = u.max_sweeps;
     t.struct_size = sizeof t;
-    t.block = aca::batch_block_size();
+    t.block = 0;     // chosen per launch from the regions' LDS (512 or 1024)
     *out = t;
     return ACA_OK;
 }

@@ -224,7 +224,8 @@ struct BatchGlobal {
 // Host side of the batch kernels (aca_batch.hip).
 size_t batch_lds_bytes(int dim, const VisitArgs &a);
 hipError_t set_batch_lds_limit(size_t bytes);
-int batch_block_size();
+// Threads per workgroup of the persistent visit (for regions of `lds` bytes).
+int batch_block_size(size_t lds);
 // Resident blocks of the visit kernel for `dim` (0 = mixed) on this device.
 hipError_t batch_max_blocks(int dim, size_t lds, int *blocks);
 // Pack the members listed in `joining` (state zeroed, snapshot 1 and tile
