@@ -291,12 +291,16 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
         const uint32_t in = epoch & 1u;
         const region::Snapshots io{sl.key[in], sl.time[in], sl.key[in ^ 1u], sl.time[in ^ 1u]};
         region::RegionTally r;
+        // unit-rate lattices take the visit without the division by the rate
         if (DIM == 2 || (DIM == 0 && sl.dim == 2))
-            r = region::visit_region<2>(a, io, tile, lds);
+            r = a.unit_rate ? region::visit_region<2, false, 1, true>(a, io, tile, lds)
+                            : region::visit_region<2>(a, io, tile, lds);
         else if (DIM == 3 || (DIM == 0 && sl.dim == 3))
-            r = region::visit_region<3>(a, io, tile, lds);
+            r = a.unit_rate ? region::visit_region<3, false, 1, true>(a, io, tile, lds)
+                            : region::visit_region<3>(a, io, tile, lds);
         else
-            r = region::visit_region<1>(a, io, tile, lds);
+            r = a.unit_rate ? region::visit_region<1, false, 1, true>(a, io, tile, lds)
+                            : region::visit_region<1>(a, io, tile, lds);
         if (threadIdx.x == 0) {
             BatchState &st = state[slot];
             if (!r.skipped) {

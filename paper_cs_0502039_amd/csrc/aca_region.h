@@ -8,8 +8,11 @@
 // it can prove is the next one of its cell (Fig. 3.1's test, with ties broken
 // by global index) in rounds over worklists, and merges every owned copy and
 // every moved ghost copy into the output snapshot with an element-wise
-// maximum (all copies are prefixes of the one trajectory, so the maximum is
-// the most advanced copy).  Layout for speed on the large lattices:
+// maximum.  All copies are prefixes of the one trajectory, so the maximum is
+// the most advanced copy; the merge must take it, because a neighbouring
+// region may have advanced its own cells on a ghost copy that got further
+// than the owner's (the snapshot has to stay a consistent cut).  Layout for
+// speed on the large lattices:
 //
 //  * LDS holds the region box with fixed pitches (the largest box of the
 //    plan), so the neighbours of a cell are constant index offsets and the
@@ -21,7 +24,12 @@
 //  * the enabling test compares times strictly; only when a candidate's time
 //    equals a neighbour's (rare in binary64) does the wavefront take the path
 //    that resolves the tie by global index;
-//  * the newly enabled cells of a wavefront are appended with one LDS atomic.
+//  * the newly enabled cells of a wavefront are appended with one LDS atomic;
+//  * a worklist never holds two cells that read each other (both could not
+//    be enabled at once, and a listed cell stays enabled until it applies),
+//    so a cell is re-tested by several lanes of a round only as a neighbour
+//    of cells they applied: only those pushes take a claim bit, cleared when
+//    the cell is taken from the list.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -217,8 +225,9 @@ struct Snapshots {
 // instantiation, so the visit without frames carries none of its registers).
 // Q: the reach of the rule (q-th degree neighbourhood); the frozen ring is Q
 // cells wide.  Q = 1 is the nearest-neighbour visit tuned above; Q > 1 tests
-// and sums over the ball offsets directly.
-template <int DIM, bool FRAMES = false, int Q = 1>
+// and sums over the ball offsets directly.  UNIT: the lattice's rate is 1, so
+// the gap is -ln u itself (the general instantiation divides by the rate).
+template <int DIM, bool FRAMES = false, int Q = 1, bool UNIT = false>
 __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Snapshots io,
                                                     uint32_t tile, unsigned char *lds)
 {
@@ -385,7 +394,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     const double horizon_t = __longlong_as_double((long long)horizon);
     const uint64_t final_bits = a.final_bits;
     const double final_t = __longlong_as_double((long long)final_bits);
-    const bool unit_rate = a.unit_rate != 0;
+    const bool unit_rate = UNIT || a.unit_rate != 0;
     uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
 
     // Box offset of stencil entry k.
@@ -457,7 +466,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             en = enabled_q(bi, wc, tie);
             if (tie) en = exact_q(bi, q, wc);
             ++my_checks;
-            if (en) atomicOr(&claim[bi >> 5], 1u << (bi & 31));
         } else if (Q == 1 && j < boxp && is_inner(q)) {
             const uint64_t wc = ldw(&ts[bi]);
             uint64_t tn[Z];
@@ -477,7 +485,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 en = exact(wc & kMask, tn, q);
             }
             ++my_checks;
-            if (en) atomicOr(&claim[bi >> 5], 1u << (bi & 31));
         }
         const uint64_t m = __ballot(en);
         if (m) {
@@ -563,7 +570,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                     if (__ballot(tie)) {
                         if (tie) want = exact_q(xb, qx, wx);
                     }
-                    if (want) {
+                    if (want && k >= 0) {
                         const uint32_t bit = 1u << (xb & 31);
                         want = (atomicOr(&claim[xb >> 5], bit) & bit) == 0u;
                     }
@@ -677,12 +684,13 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                     }
                 }
             }
-            // claim; a cell already claimed by another lane is not listed twice
+            // claim the neighbours; one already claimed by another lane is not
+            // listed twice (the applied cell itself is tested by this lane only)
             int cb[Z + 1];
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
                 cb[s] = bi + off(s);
-                if (want[s]) {
+                if (s > 0 && want[s]) {
                     const uint32_t bit = 1u << (cb[s] & 31);
                     want[s] = (atomicOr(&claim[cb[s] >> 5], bit) & bit) == 0u;
                 }

@@ -19,7 +19,17 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
     const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                                       (unsigned)a.ntiles[2];
     const region::Snapshots io{a.key_in, a.time_in, a.key_out, a.time_out};
-    const region::RegionTally r = region::visit_region<DIM, FRAMES, Q>(a, io, blockIdx.x, lds);
+    region::RegionTally r;
+    if constexpr (Q == 1 && !FRAMES) {
+        // the nearest-neighbour visit without frames has a unit-rate variant
+        // (no division in the gap); the branch is uniform over the launch
+        if (a.unit_rate)
+            r = region::visit_region<DIM, false, 1, true>(a, io, blockIdx.x, lds);
+        else
+            r = region::visit_region<DIM, false, 1, false>(a, io, blockIdx.x, lds);
+    } else {
+        r = region::visit_region<DIM, FRAMES, Q>(a, io, blockIdx.x, lds);
+    }
     if (threadIdx.x == 0) {
         if (!r.skipped) {
             unsigned long long *gc = a.counters;
