@@ -93,10 +93,16 @@ __device__ __forceinline__ void capture_frames(
 // Called by thread 0 of every block of a visit launch after it has added its
 // counters.  The last block to finish (ticket ntiles - 1) publishes the slot's
 // counters to pinned host memory and clears the slot for its next use, so a
-// launch needs no separate memset or copy command.
+// launch needs no separate memset or copy command.  The counters and the
+// ticket are device-scope atomics, performed where all blocks see them: the
+// ticket only has to wait until this block's counter atomics have completed
+// (a full release fence here would also write back the L2 on every block;
+// the block's other writes are read by later launches only).
 __device__ inline void finish_visit_block(const VisitArgs &a, unsigned int ntiles)
 {
-    __threadfence();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);   // vmcnt, expcnt and lgkmcnt all zero
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const unsigned int ticket = atomicAdd(a.done_blocks, 1u);
     if (ticket == ntiles - 1u) {
         __threadfence();

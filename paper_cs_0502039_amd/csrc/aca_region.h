@@ -70,6 +70,13 @@ __device__ __forceinline__ void stw(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Number of lanes below this one whose bit is set in the wavefront mask m.
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Pending time of a packed word: the spin is the sign bit and every time is
 // positive, so |word as binary64| is the time (a free source modifier), and
 // binary64 order on these values is the order of their bit patterns.
@@ -491,7 +498,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             int b0 = 0;
             if (lane == 0) b0 = atomicAdd(&sizes[0], (int)__popcll(m));
             b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
-            if (en) lists[b0 + (int)__popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)bi;
+            if (en) lists[b0 + lanes_below(m)] = (uint16_t)bi;
         }
     }
     __syncthreads();
@@ -551,7 +558,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 // re-test the applied cell and every cell of its ball (they
                 // hold it in theirs) once this lane's arrival is published
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-                const uint64_t below = (1ull << lane) - 1ull;
                 for (int k = -1; k < ZQ; ++k) {
                     int qx[3] = {q[0], q[1], q[2]};
                     int xb = bi;
@@ -579,7 +585,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                         int b0 = 0;
                         if (lane == 0) b0 = atomicAdd(next_size, (int)__popcll(mk));
                         b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
-                        if (want) lnext[b0 + (int)__popcll(mk & below)] = (uint16_t)xb;
+                        if (want) lnext[b0 + lanes_below(mk)] = (uint16_t)xb;
                     }
                 }
                 continue;
@@ -707,10 +713,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 int b0 = 0;
                 if (lane == 0) b0 = atomicAdd(next_size, total);
                 b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
-                const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
                 for (int s = 0; s <= Z; ++s) {
-                    if (want[s]) lnext[b0 + (int)__popcll(mk[s] & below)] = (uint16_t)cb[s];
+                    if (want[s]) lnext[b0 + lanes_below(mk[s])] = (uint16_t)cb[s];
                     b0 += (int)__popcll(mk[s]);
                 }
             }
