@@ -152,12 +152,15 @@ aca_status aca_get_tuning(const aca_lattice *lat, aca_tuning *out);
 aca_status aca_init(aca_lattice *lat, void *stream);
 
 /* Declare that the state buffers already hold a state advanced to horizon
- * T_done (e.g. restored from a checkpoint); resets the statistics. */
+ * T_done (e.g. restored from a checkpoint); resets the statistics.  Every
+ * count n(c) must be below 2^31. */
 aca_status aca_resume(aca_lattice *lat, double T_done);
 
 /* Apply every arrival with time < T, in the conservative parallel schedule.
  * Returns when done (the state is in the caller's buffers and the stream is
- * synchronised).  T must be finite and >= the last horizon (equal: no-op).
+ * synchronised).  T must be finite and >= the last horizon (equal: no-op),
+ * and rate * T <= 2^30 (ACA_EINVAL otherwise: counts are kept below 2^31;
+ * the same bound applies to aca_batch_attach and aca_server_submit).
  * Afterwards t(c) is the first arrival at or after T and n(c) counts the
  * arrivals applied since time 0. */
 aca_status aca_advance(aca_lattice *lat, double T, void *stream);

@@ -556,6 +556,9 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
     if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     if (!lat->initialized) return fail(ACA_ESTATE, "aca_init (or aca_resume) first");
     if (!is_finite(T)) return fail(ACA_EINVAL, "horizon must be finite");
+    if (!aca_host::horizon_fits_counts(lat->p.rate, T))
+        return fail(ACA_EINVAL, "rate * horizon = %.17g exceeds 2^30 (arrival counts are 31-bit)",
+                    lat->p.rate * T);
     if (T < lat->last_T)
         return fail(ACA_EINVAL, "horizon %.17g is before the last one %.17g", T,
                     lat->last_T);

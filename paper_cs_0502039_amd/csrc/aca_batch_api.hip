@@ -326,6 +326,9 @@ ACA_EXPORT aca_status aca_batch_attach(aca_batch *b, aca_lattice *lat, double T)
     if (!is_finite(T) || T < lat->last_T || T <= 0.0)
         return fail(ACA_EINVAL, "horizon %.17g must be finite, > 0 and >= the last one %.17g",
                     T, lat->last_T);
+    if (!aca_host::horizon_fits_counts(lat->p.rate, T))
+        return fail(ACA_EINVAL, "rate * horizon = %.17g exceeds 2^30 (arrival counts are 31-bit)",
+                    lat->p.rate * T);
     int slot = -1;
     for (int i = 0; i < b->capacity; ++i)
         if (!b->member[i].lat) { slot = i; break; }

@@ -30,6 +30,12 @@ aca_status fail(aca_status code, const char *fmt, ...) __attribute__((format(pri
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
+// Arrival counts stay below 2^31 (a region's LDS count word keeps a claim bit
+// above them): a horizon is accepted while rate * T <= 2^30, so that 2^31
+// arrivals of one cell would lie some 2^15 standard deviations out.
+constexpr double kMaxMeanArrivals = 1073741824.0;
+inline bool horizon_fits_counts(double rate, double T) { return rate * T <= kMaxMeanArrivals; }
+
 // Scratch: two snapshots of working words (key, time), one flag byte per
 // cell for tile flags (a tile holds at least one cell), and the counters.
 struct ScratchLayout {

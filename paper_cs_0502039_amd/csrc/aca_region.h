@@ -28,8 +28,9 @@
 //  * a worklist never holds two cells that read each other (both could not
 //    be enabled at once, and a listed cell stays enabled until it applies),
 //    so a cell is re-tested by several lanes of a round only as a neighbour
-//    of cells they applied: only those pushes take a claim bit, cleared when
-//    the cell is taken from the list.
+//    of cells they applied: only those pushes take a claim, bit 31 of the
+//    cell's arrival-count word (counts stay below 2^31), which the lane that
+//    applies the cell's next arrival clears when it writes the new count.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,6 +70,11 @@ __device__ __forceinline__ void stw(uint64_t *p, uint64_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// A region cell's LDS count word: its arrival count n (< 2^31) and, in bit
+// 31, the claim of a cell listed by a neighbour's lane.
+constexpr uint32_t kClaim = 0x80000000u;
+constexpr uint32_t kCountMask = 0x7FFFFFFFu;
 
 // Number of lanes below this one whose bit is set in the wavefront mask m.
 __device__ __forceinline__ int lanes_below(uint64_t m)
@@ -172,8 +178,8 @@ struct Ball {
 };
 
 struct FastPlan {
-    size_t thr_off, ctr_off, tmin_off, ball_off, tab_off, ts_off, n_off, f_off, claim_off,
-        list_off, list_cap, total;
+    size_t thr_off, ctr_off, tmin_off, ball_off, tab_off, ts_off, n_off, f_off, list_off,
+        list_cap, total;
 };
 
 // Pitched box: pitch[d] = the largest region box side along d in this launch.
@@ -211,10 +217,9 @@ __host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim)
     const size_t guard = 2 * (size_t)pitch[0];
     p.ts_off = (p.tab_off + 4 * (size_t)(pitch[0] + pitch[1] + pitch[2]) + 7) & ~(size_t)7;
     p.ts_off += 8 * guard;
-    p.n_off = p.ts_off + 8 * (boxp + guard);                    // uint32 n[boxp]
+    p.n_off = p.ts_off + 8 * (boxp + guard);                    // uint32 n[boxp] | claim
     p.f_off = p.n_off + 4 * boxp;                               // uint16 f[boxp]
-    p.claim_off = (p.f_off + 2 * boxp + 3) & ~(size_t)3;        // uint32 bits
-    p.list_off = p.claim_off + 4 * ((boxp + 31) / 32);
+    p.list_off = (p.f_off + 2 * boxp + 3) & ~(size_t)3;
     p.list_cap = (size_t)inner / 2 + 2;                         // uint16 list[2][cap]
     p.total = (p.list_off + 4 * p.list_cap + 15) & ~(size_t)15;
     return p;
@@ -290,13 +295,12 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     uint64_t *ts = reinterpret_cast<uint64_t *>(lds + plan.ts_off);
     uint32_t *nl = reinterpret_cast<uint32_t *>(lds + plan.n_off);
     uint16_t *fl = reinterpret_cast<uint16_t *>(lds + plan.f_off);
-    uint32_t *claim = reinterpret_cast<uint32_t *>(lds + plan.claim_off);
     uint16_t *lists = reinterpret_cast<uint16_t *>(lds + plan.list_off);
     const int cap = (int)plan.list_cap;
     int *sizes = ctr;        // [0..2] list lengths, rotating over rounds
     int *takes = ctr + 3;    // [3..5] take positions, rotating over rounds
 
-    // ---- tables: global offsets of box rows/columns/planes; clear claims
+    // ---- tables: global offsets of box rows/columns/planes
     uint64_t *tmin_slot = reinterpret_cast<uint64_t *>(lds + plan.tmin_off);
     // Q > 1: box offset and packed coordinate step of every ball entry
     int *ball_box = reinterpret_cast<int *>(lds + plan.ball_off);
@@ -320,7 +324,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         tz[j] = (uint32_t)(DIM > 2 ? wrap_into(org[2] + j, side[2]) : 0) * (uint32_t)side[0] *
                 (uint32_t)side[1];
     const int boxp = pitch[0] * pitch[1] * pitch[2];
-    for (int j = tid; j < (boxp + 31) / 32; j += nthreads) claim[j] = 0u;
     __syncthreads();
 
     // Box index j = q0 + P1 (q1 + pitch1 q2) of a cell, decoded with the
@@ -460,7 +463,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 
     int rounds = 0;
     if (own_due) {
-    // ---- initial scan: every enabled simulated cell, claimed, into list 0
+    // ---- initial scan: every enabled simulated cell into list 0
     for (int base = tid - lane; base < boxp; base += nthreads) {
         const int j = base + lane;
         bool en = false;
@@ -527,11 +530,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 if (active) {
                     bi = lcur[start + lane];
                     decode(bi, q);
-                    atomicAnd(&claim[bi >> 5], ~(1u << (bi & 31)));
                     const uint64_t w0 = ldw(&ts[bi]);
                     int sum = 0;
                     for (int k = 0; k < ZQ; ++k) sum += (ldw(&ts[bi + ball_box[k]]) >> 63) ? -1 : 1;
-                    const uint32_t kn = nl[bi];
+                    const uint32_t kn = nl[bi] & kCountMask;   // claim bit off
                     const uint32_t gidx = gidx_at(q);
                     const Draw y = philox4x32_10(kn, gidx, 0u, 0u, a.key_lo, a.key_hi);
                     const int idx = (sum + ZQ) / 2 + (ZQ + 1) * ((w0 >> 63) ? 0 : 1);
@@ -576,10 +578,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                     if (__ballot(tie)) {
                         if (tie) want = exact_q(xb, qx, wx);
                     }
-                    if (want && k >= 0) {
-                        const uint32_t bit = 1u << (xb & 31);
-                        want = (atomicOr(&claim[xb >> 5], bit) & bit) == 0u;
-                    }
+                    if (want && k >= 0) want = (atomicOr(&nl[xb], kClaim) & kClaim) == 0u;
                     const uint64_t mk = __ballot(want);
                     if (mk) {
                         int b0 = 0;
@@ -602,7 +601,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 } else {
                     q[1] = row;
                 }
-                atomicAnd(&claim[bi >> 5], ~(1u << (bi & 31)));
                 // the cell and its neighbour slots: stable until it applies
                 // its arrival (no neighbour can be enabled meanwhile)
 #pragma unroll
@@ -610,7 +608,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 int sum = 0;
 #pragma unroll
                 for (int j = 1; j <= Z; ++j) sum += (W[j] >> 63) ? -1 : 1;
-                const uint32_t kn = nl[bi];
+                const uint32_t kn = nl[bi] & kCountMask;   // claim bit off
                 const uint32_t gidx = tx[q[0]] + ty[q[1]] + tz[q[2]];
                 const Draw y = philox4x32_10(kn, gidx, 0u, 0u, a.key_lo, a.key_hi);
                 const int idx = (sum + Z) / 2 + (Z + 1) * ((W[0] >> 63) ? 0 : 1);
@@ -696,10 +694,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
                 cb[s] = bi + off(s);
-                if (s > 0 && want[s]) {
-                    const uint32_t bit = 1u << (cb[s] & 31);
-                    want[s] = (atomicOr(&claim[cb[s] >> 5], bit) & bit) == 0u;
-                }
+                if (s > 0 && want[s]) want[s] = (atomicOr(&nl[cb[s]], kClaim) & kClaim) == 0u;
             }
             // one LDS atomic per wavefront for all its new list entries
             uint64_t mk[Z + 1];
@@ -745,7 +740,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         for (int u = 0; u < U; ++u) {
             if (!inn[u]) continue;
             const int bi = j0 + u * nthreads;
-            const uint32_t n_copy = nl[bi];
+            const uint32_t n_copy = nl[bi] & kCountMask;   // a listed cell may be claimed
             const uint64_t wd = ts[bi];
             if (own[u] || n_copy != (uint32_t)(key_in[u] >> 32)) {
                 const unsigned long long f = ((key_in[u] >> 1) & 0x7FFFFFFFull) + fl[bi];

@@ -253,6 +253,9 @@ ACA_EXPORT aca_status aca_server_submit(aca_server *srv, const aca_params *p, do
     st = job_layout(p, &l);
     if (st != ACA_OK) return st;
     if (!is_finite(T) || T <= 0.0) return fail(ACA_EINVAL, "horizon must be finite and > 0");
+    if (!aca_host::horizon_fits_counts(p->rate, T))
+        return fail(ACA_EINVAL, "rate * horizon = %.17g exceeds 2^30 (arrival counts are 31-bit)",
+                    p->rate * T);
     if (l.total > srv->alloc.size())
         return fail(ACA_ENOMEM, "job needs %llu arena bytes, the arena has %llu",
                     (unsigned long long)l.total, (unsigned long long)srv->alloc.size());

@@ -193,6 +193,9 @@ def test_batch_state_errors(torch):
     with pytest.raises(aca.AcaError) as e:
         batch.attach(other, 1.0)
     assert e.value.code == aca.ACA_ESTATE
+    with pytest.raises(aca.AcaError) as e:
+        batch.attach(lat, 2.0 ** 31)  # rate * T > 2^30
+    assert e.value.code == aca.ACA_EINVAL
     batch.attach(lat, 2.0)
     with pytest.raises(aca.AcaError) as e:
         batch.attach(lat, 2.0)

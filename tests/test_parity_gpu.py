@@ -190,6 +190,9 @@ def test_error_paths(torch):
     with pytest.raises(aca.AcaError) as e:
         lat.advance(float("nan"))
     assert e.value.code == aca.ACA_EINVAL
+    with pytest.raises(aca.AcaError) as e:
+        lat.advance(2.0 ** 31)                          # rate * T > 2^30: counts are 31-bit
+    assert e.value.code == aca.ACA_EINVAL and "2^30" in str(e.value)
     before = lat.read()
     lat.advance(2.0)                                    # same horizon: no-op
     assert_same_state(lat.read(), before, "no-op")

@@ -151,6 +151,9 @@ def test_server_state_errors(torch):
     with pytest.raises(aca.AcaError) as e:
         server.submit(workloads.lattice(2, (512, 512), 0.3, T=1.0))   # never fits
     assert e.value.code == aca.ACA_ENOMEM
+    with pytest.raises(aca.AcaError) as e:
+        server.submit(workloads.lattice(2, (48, 48), 0.3, T=2.0 ** 31))  # rate * T > 2^30
+    assert e.value.code == aca.ACA_EINVAL
     job = server.submit(p)
     with pytest.raises(aca.AcaError) as e:
         server.read(job)                     # queued
