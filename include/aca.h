@@ -130,8 +130,8 @@ aca_status aca_thresholds(const aca_params *p, uint64_t *out, int32_t cap,
                           int32_t *count);
 
 /* Sizes for p: number of cells, and bytes of device scratch the caller must
- * provide to aca_create (two working snapshots of 16 bytes per cell plus
- * counters; 32 N + 256 bytes). */
+ * provide to aca_create (two working snapshots of 16 bytes per cell, a byte
+ * per cell for per-tile flags, and counters: about 33 N + 512 bytes). */
 aca_status aca_query(const aca_params *p, uint64_t *n_cells,
                      uint64_t *scratch_bytes);
 

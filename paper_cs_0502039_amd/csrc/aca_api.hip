@@ -433,6 +433,11 @@ ACA_EXPORT aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_
         ok = hipEventCreate(&lat->ev_start[i]) == hipSuccess &&
              hipEventCreate(&lat->ev_stop[i]) == hipSuccess;
     if (!ok) {
+        for (int i = 0; i < 2; ++i) {
+            if (lat->ev_start[i]) (void)hipEventDestroy(lat->ev_start[i]);
+            if (lat->ev_stop[i]) (void)hipEventDestroy(lat->ev_stop[i]);
+        }
+        if (lat->host_ctr) (void)hipHostFree(lat->host_ctr);
         delete lat;
         return fail(ACA_EDEVICE, "pinned host word or HIP event creation failed");
     }
