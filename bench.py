@@ -70,16 +70,22 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, launches: int):
+def measured_traffic(workload: str, tuning: dict):
     """HBM bytes per visit launch from the committed counter summary
     (profiles/traffic_<workload>.json, FETCH_SIZE + WRITE_SIZE scaled by a copy
-    kernel's readings), or None when it is missing or the kernels changed since."""
+    kernel's readings), or None when it is missing, the kernels changed since,
+    or the counters were taken with other tiles, ghosts or block size (a
+    launch's loads and merges depend on those, not on the rounds per visit)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         doc = json.load(f)
     if doc.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    prof = doc.get("tuning", {})
+    if any(list(prof.get(k, [])) != list(tuning.get(k, [])) for k in ("tile", "ghost")) or \
+            prof.get("block") != tuning.get("block"):
         return None
     return doc["hbm_bytes_per_launch"]
 
@@ -443,7 +449,7 @@ def main() -> int:
     ev_launch = events / launches
     alu_achieved = ev_launch / t_launch / 1e9                  # Gevents/s
     alu_peak = VALU_LANE_OPS_PER_S / SLOTS_PER_EVENT / 1e9      # Gevents/s
-    traffic = measured_traffic(args.workload, launches)
+    traffic = measured_traffic(args.workload, lat.tuning())
     hbm = {"bound": "hbm", "achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": hbm_achieved / HBM_PEAK_GBS, "traffic": traffic}
     alu = {"bound": "alu", "achieved": alu_achieved, "peak": alu_peak,
