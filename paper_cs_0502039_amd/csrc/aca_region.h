@@ -385,8 +385,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             if (!ok[u]) continue;
             const int bi = j0 + u * nthreads;
             ts[bi] = (uint64_t)tb[u] | ((key[u] & 1ull) << 63);
+            // a ring cell carries a claim that is never cleared: a re-test
+            // that finds it enabled can never list it
+            nl[bi] = inn[u] ? (uint32_t)(key[u] >> 32) : kClaim;
             if (inn[u]) {
-                nl[bi] = (uint32_t)(key[u] >> 32);
                 fl[bi] = 0;
                 due = due || (own[u] && (uint64_t)tb[u] < a.final_bits);
                 if (own[u] && (uint64_t)tb[u] < tmin_own) tmin_own = (uint64_t)tb[u];
@@ -405,7 +407,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     const uint64_t final_bits = a.final_bits;
     const double final_t = __longlong_as_double((long long)final_bits);
     const bool unit_rate = UNIT || a.unit_rate != 0;
-    uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0;
+    // events, flips and ghost events are counted at the merge (count after -
+    // count loaded); re-tests are 2 dim + 1 per arrival applied (reach 1)
+    uint32_t my_events = 0, my_flips = 0, my_ghost = 0, my_checks = 0, my_applied = 0;
 
     // Box offset of stencil entry k.
     auto off = [&](int k) { return S.d[k][0] + P1 * S.d[k][1] + P12 * S.d[k][2]; };
@@ -550,12 +554,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                     fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     stw(&ts[bi], wnew);
-                    if (is_own(q)) {
-                        ++my_events;
-                        my_flips += flip ? 1u : 0u;
-                    } else {
-                        ++my_ghost;
-                    }
                 }
                 // re-test the applied cell and every cell of its ball (they
                 // hold it in theirs) once this lane's arrival is published
@@ -625,15 +623,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 stw(&ts[bi], wnew);
                 W[0] = wnew;
-                bool own = true;
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) own = own && q[d] >= olo[d] && q[d] < ohi[d];
-                if (own) {
-                    ++my_events;
-                    my_flips += flip ? 1u : 0u;
-                } else {
-                    ++my_ghost;
-                }
+                ++my_applied;
             }
             // The rest of the neighbourhood is read only after this lane's
             // arrival is published: of two cells that share a neighbour and
@@ -659,21 +649,15 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             bool any_tie = false;
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
-                bool inside = active;
-                if (s > 0) {
-                    const int ax = (s - 1) >> 1;
-                    const int qs = q[ax] + (((s - 1) & 1) ? -1 : 1);
-                    inside = inside && qs >= 1 && qs <= rin[ax];
-                }
+                // a ring neighbour is tested too; its claim never succeeds
                 const double tc = time_of(W[s]);
                 double tmin = time_of(W[S.nb[s][0]]);
 #pragma unroll
                 for (int j = 1; j < Z; ++j) tmin = __builtin_fmin(tmin, time_of(W[S.nb[s][j]]));
-                const bool live = inside && tc < horizon_t;
+                const bool live = active && tc < horizon_t;
                 want[s] = live && tc < tmin;
                 tie[s] = live && tc == tmin;
                 any_tie = any_tie || tie[s];
-                my_checks += inside ? 1u : 0u;
             }
             if (__ballot(any_tie)) {
 #pragma unroll
@@ -742,7 +726,14 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             const int bi = j0 + u * nthreads;
             const uint32_t n_copy = nl[bi] & kCountMask;   // a listed cell may be claimed
             const uint64_t wd = ts[bi];
-            if (own[u] || n_copy != (uint32_t)(key_in[u] >> 32)) {
+            const uint32_t moved = n_copy - (uint32_t)(key_in[u] >> 32);
+            if (own[u]) {
+                my_events += moved;
+                my_flips += fl[bi];
+            } else {
+                my_ghost += moved;
+            }
+            if (own[u] || moved != 0u) {
                 const unsigned long long f = ((key_in[u] >> 1) & 0x7FFFFFFFull) + fl[bi];
                 atomicMax(&io.key_out[gi[u]],
                           ((unsigned long long)n_copy << 32) | (f << 1) | (wd >> 63));
@@ -754,7 +745,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     atomicAdd(&ctr[6], (int)my_events);
     atomicAdd(&ctr[7], (int)my_flips);
     atomicAdd(&ctr[8], (int)my_ghost);
-    atomicAdd(&ctr[9], (int)my_checks);
+    atomicAdd(&ctr[9], (int)(my_checks + (Q == 1 ? (uint32_t)(Z + 1) * my_applied : 0u)));
     const int any_live = __syncthreads_or(live ? 1 : 0);
     return RegionTally{(uint32_t)ctr[6], (uint32_t)ctr[7], (uint32_t)ctr[8], (uint32_t)ctr[9],
                        rounds, own_due, any_live, 0};
