@@ -72,7 +72,8 @@ __device__ __forceinline__ void stw(uint64_t *p, uint64_t v)
 }
 
 // A region cell's LDS count word: its arrival count n (< 2^31) and, in bit
-// 31, the claim of a cell listed by a neighbour's lane.
+// 31, the claim of a cell listed by a neighbour's lane (always set on the
+// frozen ring, whose cells are never listed).
 constexpr uint32_t kClaim = 0x80000000u;
 constexpr uint32_t kCountMask = 0x7FFFFFFFu;
 
