@@ -217,6 +217,12 @@ __device__ bool claim_item(const BatchSlot *slots, BatchState *state, const uint
             return false;
         }
         __builtin_amdgcn_s_sleep(32);
+        // The claim words are read with device-scope loads, which this XCD's
+        // L2 may still serve from a line cached before another compute unit
+        // opened an epoch (lines of memory not local to an L2 are not kept
+        // coherent).  Items that start a visit invalidate it; when every
+        // workgroup here is waiting, this acquire does.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
 }
 
