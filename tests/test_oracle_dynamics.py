@@ -235,6 +235,33 @@ def test_initial_state_law():
     assert np.array_equal(t2, t / 4.0)                 # exact: division by 4
 
 
+@pytest.mark.parametrize("rule,beta,h", [("glauber", 0.7, 0.3), ("metropolis", 0.5, -0.4),
+                                          ("glauber", 1.3, -0.25)])
+@pytest.mark.parametrize("init", ["plus", "minus"])
+def test_independent_spins_closed_form(rule, beta, h, init):
+    """J = 0: every cell is a two-state chain of its own.  An arrival reverses a
+    +1 spin with probability a = thr[+]/2^32 and a -1 spin with b = thr[-]/2^32
+    (Section 2's rule with the field alone), so at unit rate
+    P(s = +1, t) = pi + (P0 - pi) exp(-(a + b) t), pi = b / (a + b).
+    A sign slip in the field or the spin side of the table fails this."""
+    N, T = 40000, 1.2
+    params = P(1, (N,), beta, rule, J=0.0, h=h, init=init, seed=77)
+    thr = oracle.thresholds(1, 0.0, h, beta, rule).astype(np.float64) / 2.0 ** 32
+    z = 2
+    a, b = thr[z + 1], thr[0]           # spin +1 entries follow the spin -1 ones
+    assert np.all(thr[z + 1:] == a) and np.all(thr[:z + 1] == b)
+    pi = b / (a + b)
+    p0 = 1.0 if init == "plus" else 0.0
+    want = pi + (p0 - pi) * math.exp(-(a + b) * T)
+    s, _, _, _, _ = oracle.simulate(params, T)
+    got = float(np.mean(s == 1))
+    sigma = math.sqrt(want * (1.0 - want) / N)
+    assert abs(got - want) < 5.0 * sigma, (got, want, sigma)
+    # power: the field's sign swapped gives a clearly different value
+    swapped = (1.0 - pi) + (p0 - (1.0 - pi)) * math.exp(-(a + b) * T)
+    assert abs(swapped - want) > 20.0 * sigma
+
+
 def test_poisson_counts_and_cell_clock():
     params = P(2, (64, 64), 0.4406868, seed=2)
     T = 30.0
