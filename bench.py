@@ -365,7 +365,10 @@ def main() -> int:
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-arena-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=512)
-    ap.add_argument("--serve-budget-ms", type=float, default=2.0)
+    # device time per server step: longer steps spread the per-step host work
+    # (admission, pack/unpack, the counter read-back) over more epochs; the
+    # step length also bounds how long a finished job waits to be reported
+    ap.add_argument("--serve-budget-ms", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the workload is a single "
