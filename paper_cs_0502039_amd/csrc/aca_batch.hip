@@ -230,34 +230,41 @@ __device__ bool claim_item(const BatchSlot *slots, BatchState *state, const uint
 // open the next epoch, or pause (step budget) or retire the member.
 __device__ void close_epoch(BatchState &st, uint32_t epoch, BatchGlobal *g)
 {
-    __threadfence();     // every tile's merge of this epoch is visible
+    // every tile's merge and counters of this epoch were performed before its
+    // ticket; drop lines this XCD cached before them
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t live = ld_agent32(&st.live);
     const unsigned long long moves = ld_agent(&st.epoch_moves);
     const uint32_t next = epoch + 1u;
     st_agent32(&st.finished, 0u);
     st_agent32(&st.live, 0u);
     st_agent(&st.epoch_moves, 0ull);
-    const uint32_t done_epochs = st.epochs + 1u;
-    st.epochs = done_epochs;
-    st.total_epochs += 1u;
+    // the closer of the next epoch may run on another XCD: device-scope words
+    const uint32_t done_epochs = ld_agent32(&st.epochs) + 1u;
+    st_agent32(&st.epochs, done_epochs);
+    st_agent32(&st.total_epochs, ld_agent32(&st.total_epochs) + 1u);
     const unsigned long long closed = ((unsigned long long)next << 32) | kClaimClosed;
     uint32_t status = kSlotRunning;
     if (live == 0u) {
         // no owned cell before the horizon: the merged snapshot is final
-        st.final_snap = next & 1u;
+        st_agent32(&st.final_snap, next & 1u);
         status = kSlotDone;
     } else if (moves == 0ull) {
         status = kSlotStalled;
     } else if (done_epochs >= g->max_epochs || wall_clock64() >= g->deadline) {
         status = kSlotPaused;
     }
+    // the stores above (device-scope) complete before the epoch opens
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (status != kSlotRunning) {
-        st.status = status;
+        st_agent32(&st.status, status);
         st_agent(&st.claim, closed);
-        __threadfence();
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         atomicSub(&g->active, 1u);
     } else {
-        __threadfence();
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         atomicExch(&st.claim, (unsigned long long)next << 32);
     }
 }
@@ -291,7 +298,7 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
         __syncthreads();
         if (!go) return;
         // see the merges of the epoch before (and no stale cached copy)
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const BatchSlot &sl = slots[slot];
         const VisitArgs &a = sl.a;
         const uint32_t in = epoch & 1u;
@@ -307,6 +314,11 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
         else
             r = a.unit_rate ? region::visit_region<1, false, 1, true>(a, io, tile, lds)
                             : region::visit_region<1>(a, io, tile, lds);
+        // every wavefront's merge atomics have been performed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __syncthreads();
         if (threadIdx.x == 0) {
             BatchState &st = state[slot];
             if (!r.skipped) {
@@ -317,9 +329,15 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
                 atomicAdd(&st.ctr[kSweeps], (unsigned long long)r.rounds);
                 atomicAdd(&st.epoch_moves, (unsigned long long)(r.events + r.ghost));
                 if (r.any_live) atomicAdd(&st.live, 1u);
-                if (!r.own_due) a.dead[tile] = 1;
+                // a later epoch's visit of this tile may run on another XCD
+                if (!r.own_due)
+                    atomicOr(reinterpret_cast<unsigned int *>(a.dead) + (tile >> 2),
+                             1u << (8u * (tile & 3u)));
             }
-            __threadfence();    // this tile's merge before its ticket
+            // this tile's merge and counters before its ticket
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             const uint32_t ticket = atomicAdd(&st.finished, 1u);
             if (ticket == sl.ntiles - 1u) close_epoch(st, epoch, g);
         }
