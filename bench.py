@@ -371,9 +371,8 @@ def main() -> int:
     ap.add_argument("--serve-budget-ms", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the workload is a single "
-              "lattice per GPU and multi-GPU runs are not part of it (see DESIGN.md, "
-              "sharding).", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the workload is a single lattice on "
+              "one device, and runs over several GPUs are not supported.", file=sys.stderr)
         return 2
 
     import torch
