@@ -251,7 +251,8 @@ __device__ void close_epoch(BatchState &st, uint32_t epoch, BatchGlobal *g)
         status = kSlotDone;
     } else if (moves == 0ull) {
         status = kSlotStalled;
-    } else if (done_epochs >= g->max_epochs || wall_clock64() >= g->deadline) {
+    } else if (done_epochs >= g->max_epochs ||
+               (unsigned long long)wall_clock64() >= g->deadline) {
         status = kSlotPaused;
     }
     // the stores above (device-scope) complete before the epoch opens

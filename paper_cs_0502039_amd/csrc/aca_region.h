@@ -283,7 +283,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     const int P1 = pitch[0], P12 = pitch[0] * pitch[1];
     const int rb[3] = {DIM > 0 ? rin[0] + 2 * Q : 1, DIM > 1 ? rin[1] + 2 * Q : 1,
                        DIM > 2 ? rin[2] + 2 * Q : 1};
-    const int inner = rin[0] * rin[1] * rin[2];
     const uint32_t magic1 = 0xFFFFFFFFu / (uint32_t)P1 + 1u;            // P1 >= 3
     const uint32_t magic2 = pitch[1] > 1 ? 0xFFFFFFFFu / (uint32_t)pitch[1] + 1u : 0u;
 
