@@ -298,7 +298,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     uint16_t *lists = reinterpret_cast<uint16_t *>(lds + plan.list_off);
     const int cap = (int)plan.list_cap;
     int *sizes = ctr;        // [0..2] list lengths, rotating over rounds
-    int *takes = ctr + 3;    // [3..5] take positions, rotating over rounds
 
     // ---- tables: global offsets of box rows/columns/planes
     uint64_t *tmin_slot = reinterpret_cast<uint64_t *>(lds + plan.tmin_off);
@@ -339,6 +338,14 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             q[2] = 0;
         }
     };
+    // global index of box coordinates q (the row and plane tables hold 0
+    // along the directions the lattice does not have)
+    auto gidx_at = [&](const int *qq) {
+        uint32_t g = tx[qq[0]];
+        if (DIM > 1) g += ty[qq[1]];
+        if (DIM > 2) g += tz[qq[2]];
+        return g;
+    };
     auto is_own = [&](const int *q) {
         bool own = true;
 #pragma unroll
@@ -369,7 +376,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             ok[u] = j < boxp && q[0] < rb[0] && q[1] < rb[1] && q[2] < rb[2];
             inn[u] = is_inner(q);
             own[u] = is_own(q);
-            gi[u] = tx[q[0]] + ty[q[1]] + tz[q[2]];
+            gi[u] = gidx_at(q);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -434,7 +441,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     };
 
     // ---- Q > 1: the rule's ball, read entry by entry
-    auto gidx_at = [&](const int *qq) { return tx[qq[0]] + ty[qq[1]] + tz[qq[2]]; };
     auto step_of = [&](int k, int *qq) {
         const int st = ball_step[k];
         qq[0] += (st & 0xFF) - 16;
@@ -515,18 +521,16 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         const int sz = sizes[rnd % 3];
         if (sz == 0) break;
         ++rounds;
-        if (tid == 0) {
-            sizes[(rnd + 2) % 3] = 0;
-            takes[(rnd + 2) % 3] = 0;
-        }
-        const uint16_t *lcur = lists + (rnd & 1) * cap;
+        if (tid == 0) sizes[(rnd + 2) % 3] = 0;
+        uint16_t *lcur = lists + (rnd & 1) * cap;
         uint16_t *lnext = lists + (1 - (rnd & 1)) * cap;
         int *next_size = &sizes[(rnd + 1) % 3];
-        for (;;) {
-            int start = 0;
-            if (lane == 0) start = atomicAdd(&takes[rnd % 3], 64);
-            start = __builtin_amdgcn_readfirstlane(start);  // lane 0 is active
-            if (start >= sz) break;
+        // wavefront w takes the 64-entry slices w, w + W, w + 2W, ... of
+        // the list (every slice costs about the same, so a fixed stride
+        // balances as well as taking slices from a shared counter)
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int nwaves = nthreads >> 6;
+        for (int start = 64 * wave; start < sz; start += 64 * nwaves) {
             const bool active = lane < sz - start;
             if constexpr (Q > 1) {
                 // ---- one arrival per lane, rule over the ball
@@ -607,7 +611,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 #pragma unroll
                 for (int j = 1; j <= Z; ++j) sum += (W[j] >> 63) ? -1 : 1;
                 const uint32_t kn = nl[bi] & kCountMask;   // claim bit off
-                const uint32_t gidx = tx[q[0]] + ty[q[1]] + tz[q[2]];
+                const uint32_t gidx = gidx_at(q);
                 const Draw y = philox4x32_10(kn, gidx, 0u, 0u, a.key_lo, a.key_hi);
                 const int idx = (sum + Z) / 2 + (Z + 1) * ((W[0] >> 63) ? 0 : 1);
                 const bool flip = (uint64_t)y.w2 < thr[idx];
@@ -642,8 +646,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 }
             }
             // re-test the applied cell (s = 0) and its neighbours (s = 1..Z):
-            // enabled when its time is below the horizon and below the least
-            // neighbour time; equal to it only on a tie of binary64 times
+            // enabled when its time is below the least of the horizon and the
+            // neighbour times; equal to it only on a tie of binary64 times
+            // (with the horizon too: the exact test then refuses the cell)
             bool want[Z + 1];
             bool tie[Z + 1];
             bool any_tie = false;
@@ -651,12 +656,11 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             for (int s = 0; s <= Z; ++s) {
                 // a ring neighbour is tested too; its claim never succeeds
                 const double tc = time_of(W[s]);
-                double tmin = time_of(W[S.nb[s][0]]);
+                double tmin = __builtin_fmin(horizon_t, time_of(W[S.nb[s][0]]));
 #pragma unroll
                 for (int j = 1; j < Z; ++j) tmin = __builtin_fmin(tmin, time_of(W[S.nb[s][j]]));
-                const bool live = active && tc < horizon_t;
-                want[s] = live && tc < tmin;
-                tie[s] = live && tc == tmin;
+                want[s] = active && tc < tmin;
+                tie[s] = active && tc == tmin;
                 any_tie = any_tie || tie[s];
             }
             if (__ballot(any_tie)) {
@@ -673,13 +677,24 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 }
             }
             // claim the neighbours; one already claimed by another lane is not
-            // listed twice (the applied cell itself is tested by this lane only)
+            // listed twice (the applied cell itself is tested by this lane only).
+            // Every active lane issues all 2 dim claims at once, or-ing 0 into
+            // the neighbours it does not want (none of them is applied in this
+            // round: they are adjacent to a listed cell), and waits once.
             int cb[Z + 1];
+            uint32_t held[Z + 1];
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
                 cb[s] = bi + off(s);
-                if (s > 0 && want[s]) want[s] = (atomicOr(&nl[cb[s]], kClaim) & kClaim) == 0u;
+                held[s] = 0u;
             }
+            if (active) {
+#pragma unroll
+                for (int s = 1; s <= Z; ++s)
+                    held[s] = atomicOr(&nl[cb[s]], want[s] ? kClaim : 0u);
+            }
+#pragma unroll
+            for (int s = 1; s <= Z; ++s) want[s] = want[s] && (held[s] & kClaim) == 0u;
             // one LDS atomic per wavefront for all its new list entries
             uint64_t mk[Z + 1];
             int total = 0;
@@ -692,10 +707,16 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 int b0 = 0;
                 if (lane == 0) b0 = atomicAdd(next_size, total);
                 b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
+                // a lane with nothing to list writes into the current list's
+                // entry it took this batch, which nothing reads again
+                if (active) {
+                    uint16_t *const spare = lcur + start + lane;
 #pragma unroll
-                for (int s = 0; s <= Z; ++s) {
-                    if (want[s]) lnext[b0 + lanes_below(mk[s])] = (uint16_t)cb[s];
-                    b0 += (int)__popcll(mk[s]);
+                    for (int s = 0; s <= Z; ++s) {
+                        uint16_t *const at = want[s] ? lnext + b0 + lanes_below(mk[s]) : spare;
+                        *at = (uint16_t)cb[s];
+                        b0 += (int)__popcll(mk[s]);
+                    }
                 }
             }
         }
@@ -716,7 +737,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             decode(min(j, boxp - 1), q);
             inn[u] = j < boxp && is_inner(q);
             own[u] = is_own(q);
-            gi[u] = tx[q[0]] + ty[q[1]] + tz[q[2]];
+            gi[u] = gidx_at(q);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) key_in[u] = inn[u] ? io.key_in[gi[u]] : 0ull;
