@@ -329,10 +329,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // reciprocal multipliers (exact: j and the pitches stay below 2^16).
     auto decode = [&](int j, int *q) {
         const int row = (int)__umulhi((uint32_t)j, magic1);
-        q[0] = j - row * P1;
+        q[0] = j - (int)__umul24((uint32_t)row, (uint32_t)P1);          // < 2^16 each
         if (DIM > 2) {
             q[2] = (int)__umulhi((uint32_t)row, magic2);
-            q[1] = row - q[2] * pitch[1];
+            q[1] = row - (int)__umul24((uint32_t)q[2], (uint32_t)pitch[1]);
         } else {
             q[1] = row;
             q[2] = 0;
@@ -596,10 +596,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             if (active) {
                 bi = lcur[start + lane];
                 const int row = (int)__umulhi((uint32_t)bi, magic1);   // q1 + pitch1 q2
-                q[0] = bi - row * P1;
+                q[0] = bi - (int)__umul24((uint32_t)row, (uint32_t)P1);
                 if (DIM > 2) {
                     q[2] = (int)__umulhi((uint32_t)row, magic2);
-                    q[1] = row - q[2] * pitch[1];
+                    q[1] = row - (int)__umul24((uint32_t)q[2], (uint32_t)pitch[1]);
                 } else {
                     q[1] = row;
                 }
@@ -607,13 +607,14 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 // its arrival (no neighbour can be enabled meanwhile)
 #pragma unroll
                 for (int k = 0; k <= Z; ++k) W[k] = ldw(&ts[bi + off(k)]);
-                int sum = 0;
+                // (sum of neighbour spins + Z) / 2 = Z - (number of -1 neighbours)
+                int neg = 0;
 #pragma unroll
-                for (int j = 1; j <= Z; ++j) sum += (W[j] >> 63) ? -1 : 1;
+                for (int j = 1; j <= Z; ++j) neg += (int)(W[j] >> 63);
                 const uint32_t kn = nl[bi] & kCountMask;   // claim bit off
                 const uint32_t gidx = gidx_at(q);
                 const Draw y = philox4x32_10(kn, gidx, 0u, 0u, a.key_lo, a.key_hi);
-                const int idx = (sum + Z) / 2 + (Z + 1) * ((W[0] >> 63) ? 0 : 1);
+                const int idx = (Z - neg) + (Z + 1) * ((W[0] >> 63) ? 0 : 1);
                 const bool flip = (uint64_t)y.w2 < thr[idx];
                 const double tnow = __longlong_as_double((long long)(W[0] & kMask));
                 const double tnext = tnow + arrival_gap(y.w0, y.w1, a.rate, unit_rate);
@@ -681,26 +682,24 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             // Every active lane issues all 2 dim claims at once, or-ing 0 into
             // the neighbours it does not want (none of them is applied in this
             // round: they are adjacent to a listed cell), and waits once.
+            // take[s] is kClaim while cell s is to be listed by this lane
             int cb[Z + 1];
-            uint32_t held[Z + 1];
+            uint32_t take[Z + 1];
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
                 cb[s] = bi + off(s);
-                held[s] = 0u;
+                take[s] = want[s] ? kClaim : 0u;
             }
             if (active) {
 #pragma unroll
-                for (int s = 1; s <= Z; ++s)
-                    held[s] = atomicOr(&nl[cb[s]], want[s] ? kClaim : 0u);
+                for (int s = 1; s <= Z; ++s) take[s] &= ~atomicOr(&nl[cb[s]], take[s]);
             }
-#pragma unroll
-            for (int s = 1; s <= Z; ++s) want[s] = want[s] && (held[s] & kClaim) == 0u;
             // one LDS atomic per wavefront for all its new list entries
             uint64_t mk[Z + 1];
             int total = 0;
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
-                mk[s] = __ballot(want[s]);
+                mk[s] = __ballot(take[s] != 0u);
                 total += (int)__popcll(mk[s]);
             }
             if (total) {
@@ -710,11 +709,12 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 // a lane with nothing to list writes into the current list's
                 // entry it took this batch, which nothing reads again
                 if (active) {
-                    uint16_t *const spare = lcur + start + lane;
+                    const int spare = (int)(lcur - lists) + start + lane;
+                    const int nbase = (int)(lnext - lists);
 #pragma unroll
                     for (int s = 0; s <= Z; ++s) {
-                        uint16_t *const at = want[s] ? lnext + b0 + lanes_below(mk[s]) : spare;
-                        *at = (uint16_t)cb[s];
+                        const int below = lanes_below(mk[s]);
+                        lists[take[s] ? nbase + b0 + below : spare] = (uint16_t)cb[s];
                         b0 += (int)__popcll(mk[s]);
                     }
                 }
