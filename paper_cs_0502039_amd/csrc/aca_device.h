@@ -33,8 +33,14 @@ __device__ __forceinline__ Draw philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     for (int round = 0; round < 10; ++round) {
         const uint32_t ka = key_lo + kWeylA * (uint32_t)round;
         const uint32_t kb = key_hi + kWeylB * (uint32_t)round;
-        const uint64_t prodA = (uint64_t)kMulA * c0;
-        const uint64_t prodB = (uint64_t)kMulB * c2;
+        uint64_t prodA = (uint64_t)kMulA * c0;
+        uint64_t prodB = (uint64_t)kMulB * c2;
+        if (round == 9) {
+            // keep the last round's products whole: one v_mad_u64_u32 each
+            // instead of separate quarter-rate high and low multiplies
+            __asm__("" : "+v"(prodA));
+            __asm__("" : "+v"(prodB));
+        }
         const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(prodB >> 32), c1, ka, 0x96);
         const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(prodA >> 32), c3, kb, 0x96);
         c1 = (uint32_t)prodB;

@@ -107,8 +107,12 @@ struct Stencil {
     static constexpr int K = 1 + 4 * DIM + 2 * DIM * (DIM - 1);
     int d[K][3];
     int nb[Z + 1][Z];   // nb[s][j]: stencil index of (candidate s) + (unit step j)
+    // Neighbours s >= 1 of the cell are paired with a perpendicular one where
+    // possible; a pair shares the diagonal cell lead[s] (-1: unpaired).
+    int partner[Z + 1];
+    int lead[Z + 1];
 
-    constexpr Stencil() : d(), nb()
+    constexpr Stencil() : d(), nb(), partner(), lead()
     {
         int k = 1;
         for (int a = 0; a < DIM; ++a)
@@ -141,6 +145,20 @@ struct Stencil {
                     if (d[q][0] == want[0] && d[q][1] == want[1] && d[q][2] == want[2])
                         nb[s][j] = q;
             }
+        for (int s = 0; s <= Z; ++s) {
+            partner[s] = -1;
+            lead[s] = -1;
+        }
+        // slot 1 + j is the unit step j; steps 2a, 2a+1 lie on axis a
+        for (int s = 1; s <= Z; ++s) {
+            if (partner[s] >= 0) continue;
+            for (int t = s + 1; t <= Z && partner[s] < 0; ++t) {
+                if (partner[t] >= 0 || (s - 1) / 2 == (t - 1) / 2) continue;
+                partner[s] = t;
+                partner[t] = s;
+                lead[s] = lead[t] = nb[s][t - 1];   // (step s) + (step t)
+            }
+        }
     }
 };
 
@@ -653,13 +671,31 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             bool want[Z + 1];
             bool tie[Z + 1];
             bool any_tie = false;
+            // (the minimum is exact, so the shared terms -- the horizon and
+            // the applied cell for s >= 1, and a diagonal for each pair of
+            // perpendicular neighbours -- are taken once)
+            const double near0 = __builtin_fmin(horizon_t, time_of(W[0]));
+            double pre[Z + 1];
+#pragma unroll
+            for (int s = 1; s <= Z; ++s) {
+                if (S.lead[s] < 0)
+                    pre[s] = near0;
+                else if (S.partner[s] < s)
+                    pre[s] = pre[S.partner[s]];
+                else
+                    pre[s] = __builtin_fmin(near0, time_of(W[S.lead[s]]));
+            }
 #pragma unroll
             for (int s = 0; s <= Z; ++s) {
                 // a ring neighbour is tested too; its claim never succeeds
                 const double tc = time_of(W[s]);
-                double tmin = __builtin_fmin(horizon_t, time_of(W[S.nb[s][0]]));
+                double tmin = s == 0 ? horizon_t : pre[s];
 #pragma unroll
-                for (int j = 1; j < Z; ++j) tmin = __builtin_fmin(tmin, time_of(W[S.nb[s][j]]));
+                for (int j = 0; j < Z; ++j) {
+                    const int k = S.nb[s][j];
+                    if (s == 0 || (k != 0 && k != S.lead[s]))
+                        tmin = __builtin_fmin(tmin, time_of(W[k]));
+                }
                 want[s] = active && tc < tmin;
                 tie[s] = active && tc == tmin;
                 any_tie = any_tie || tie[s];
