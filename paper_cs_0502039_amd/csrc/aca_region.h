@@ -491,45 +491,64 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 
     int rounds = 0;
     if (own_due) {
-    // ---- initial scan: every enabled simulated cell into list 0
-    for (int base = tid - lane; base < boxp; base += nthreads) {
-        const int j = base + lane;
-        bool en = false;
-        const int bi = j;
-        int q[3];
-        decode(min(j, boxp - 1), q);
-        if (Q > 1 && j < boxp && is_inner(q)) {
-            const uint64_t wc = ldw(&ts[bi]);
-            bool tie = false;
-            en = enabled_q(bi, wc, tie);
-            if (tie) en = exact_q(bi, q, wc);
-            ++my_checks;
-        } else if (Q == 1 && j < boxp && is_inner(q)) {
-            const uint64_t wc = ldw(&ts[bi]);
-            uint64_t tn[Z];
-            double tmin = time_of(ldw(&ts[bi + off(1)]));
-            tn[0] = 0;
+    // ---- initial scan: every enabled simulated cell into list 0, US cells
+    // per thread per step (their reads issued together, one list atomic per
+    // wavefront for all of them)
+    constexpr int US = 4;
+    for (int base = tid - lane; base < boxp; base += US * nthreads) {
+        bool en[US];
+        int cell[US];
 #pragma unroll
-            for (int k = 0; k < Z; ++k) {
-                tn[k] = ldw(&ts[bi + off(1 + k)]);
-                if (k) tmin = __builtin_fmin(tmin, time_of(tn[k]));
-            }
-            const double tc = time_of(wc);
-            const bool due = tc < horizon_t;
-            en = due && tc < tmin;
-            if (due && tc == tmin) {
+        for (int u = 0; u < US; ++u) {
+            const int j = base + u * nthreads + lane;
+            const int bi = min(j, boxp - 1);
+            cell[u] = bi;
+            en[u] = false;
+            int q[3];
+            decode(bi, q);
+            if (Q > 1 && j < boxp && is_inner(q)) {
+                const uint64_t wc = ldw(&ts[bi]);
+                bool tie = false;
+                en[u] = enabled_q(bi, wc, tie);
+                if (tie) en[u] = exact_q(bi, q, wc);
+                ++my_checks;
+            } else if (Q == 1 && j < boxp && is_inner(q)) {
+                const uint64_t wc = ldw(&ts[bi]);
+                uint64_t tn[Z];
+                double tmin = horizon_t;
 #pragma unroll
-                for (int k = 0; k < Z; ++k) tn[k] &= kMask;
-                en = exact(wc & kMask, tn, q);
+                for (int k = 0; k < Z; ++k) {
+                    tn[k] = ldw(&ts[bi + off(1 + k)]);
+                    tmin = __builtin_fmin(tmin, time_of(tn[k]));
+                }
+                // below the least of the horizon and the neighbour times; a
+                // tie (with the horizon too) takes the exact test
+                const double tc = time_of(wc);
+                en[u] = tc < tmin;
+                if (tc == tmin) {
+#pragma unroll
+                    for (int k = 0; k < Z; ++k) tn[k] &= kMask;
+                    en[u] = exact(wc & kMask, tn, q);
+                }
+                ++my_checks;
             }
-            ++my_checks;
         }
-        const uint64_t m = __ballot(en);
-        if (m) {
+        uint64_t m[US];
+        int total = 0;
+#pragma unroll
+        for (int u = 0; u < US; ++u) {
+            m[u] = __ballot(en[u]);
+            total += (int)__popcll(m[u]);
+        }
+        if (total) {
             int b0 = 0;
-            if (lane == 0) b0 = atomicAdd(&sizes[0], (int)__popcll(m));
+            if (lane == 0) b0 = atomicAdd(&sizes[0], total);
             b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
-            if (en) lists[b0 + lanes_below(m)] = (uint16_t)bi;
+#pragma unroll
+            for (int u = 0; u < US; ++u) {
+                if (en[u]) lists[b0 + lanes_below(m[u])] = (uint16_t)cell[u];
+                b0 += (int)__popcll(m[u]);
+            }
         }
     }
     __syncthreads();
