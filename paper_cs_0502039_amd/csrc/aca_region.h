@@ -685,11 +685,12 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             }
             // re-test the applied cell (s = 0) and its neighbours (s = 1..Z):
             // enabled when its time is below the least of the horizon and the
-            // neighbour times; equal to it only on a tie of binary64 times
-            // (with the horizon too: the exact test then refuses the cell)
+            // neighbour times.  The test is strict: a cell whose time equals a
+            // neighbour's (rare in binary64) is not listed even when the index
+            // rule would let it go first; it waits for the next visit's initial
+            // scan, which applies the exact (time, index) order.  Postponing an
+            // enabled arrival is always allowed, so the result is the same.
             bool want[Z + 1];
-            bool tie[Z + 1];
-            bool any_tie = false;
             // (the minimum is exact, so the shared terms -- the horizon and
             // the applied cell for s >= 1, and a diagonal for each pair of
             // perpendicular neighbours -- are taken once)
@@ -716,21 +717,6 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                         tmin = __builtin_fmin(tmin, time_of(W[k]));
                 }
                 want[s] = active && tc < tmin;
-                tie[s] = active && tc == tmin;
-                any_tie = any_tie || tie[s];
-            }
-            if (__ballot(any_tie)) {
-#pragma unroll
-                for (int s = 0; s <= Z; ++s) {
-                    if (tie[s]) {
-                        int qs[3] = {q[0], q[1], q[2]};
-                        if (s > 0) qs[(s - 1) >> 1] += ((s - 1) & 1) ? -1 : 1;
-                        uint64_t tn[Z];
-#pragma unroll
-                        for (int j = 0; j < Z; ++j) tn[j] = W[S.nb[s][j]] & kMask;
-                        want[s] = exact(W[s] & kMask, tn, qs);
-                    }
-                }
             }
             // claim the neighbours; one already claimed by another lane is not
             // listed twice (the applied cell itself is tested by this lane only).
