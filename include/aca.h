@@ -153,7 +153,9 @@ aca_status aca_init(aca_lattice *lat, void *stream);
 
 /* Declare that the state buffers already hold a state advanced to horizon
  * T_done (e.g. restored from a checkpoint); resets the statistics.  Every
- * count n(c) must be below 2^31. */
+ * count n(c) must be below 2^31: the call waits for the device (the caller's
+ * writes to the buffers may be on any stream), checks the counts there and
+ * returns ACA_EINVAL, leaving the lattice as it was, if one is not. */
 aca_status aca_resume(aca_lattice *lat, double T_done);
 
 /* Apply every arrival with time < T, in the conservative parallel schedule.

@@ -505,6 +505,15 @@ ACA_EXPORT aca_status aca_resume(aca_lattice *lat, double T_done)
     if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
     if (!is_finite(T_done) || T_done < 0.0)
         return fail(ACA_EINVAL, "T_done must be finite and >= 0");
+    // The region visits keep a claim in bit 31 of a cell's count word, so a
+    // restored count must be below 2^31.  The caller's writes to the state
+    // buffers may still be in flight on any stream: wait for the device.
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemset(lat->counters, 0, 8));
+    HIP_TRY(aca::launch_count_bound(lat->n, lat->cnt, lat->counters, nullptr));
+    unsigned long long high = 0;
+    HIP_TRY(hipMemcpy(&high, lat->counters, 8, hipMemcpyDeviceToHost));
+    if (high) return fail(ACA_EINVAL, "a restored count n(c) is 2^31 or more");
     lat->initialized = true;
     lat->last_T = T_done;
     memset(&lat->stats, 0, sizeof lat->stats);

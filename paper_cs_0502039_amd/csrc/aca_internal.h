@@ -149,6 +149,11 @@ hipError_t launch_pack(uint64_t n_cells, const int8_t *s, const double *t,
                        unsigned long long *time, unsigned long long *sum_n,
                        hipStream_t stream);
 
+// Sets *flag to 1 if some count n(c) is 2^31 or more (the region visits keep
+// a claim in bit 31 of a count word); *flag must be 0 before.
+hipError_t launch_count_bound(uint64_t n_cells, const uint32_t *n, unsigned long long *flag,
+                              hipStream_t stream);
+
 // Working words -> caller state; adds sum of n and sum of f to sums[0..1].
 hipError_t launch_unpack(uint64_t n_cells, const unsigned long long *key,
                          const unsigned long long *time, int8_t *s, double *t,

@@ -567,6 +567,17 @@ __global__ void pack_kernel(uint64_t n_cells, const int8_t *s, const double *t,
     block_add(sum_n, acc);
 }
 
+__global__ void count_bound_kernel(uint64_t n_cells, const uint32_t *n,
+                                   unsigned long long *flag)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t high = 0;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cells;
+         c += stride)
+        high |= n[c] >> 31;
+    if (__ballot(high != 0u) != 0ull && (threadIdx.x & 63u) == 0u) atomicOr(flag, 1ull);
+}
+
 __global__ void unpack_kernel(uint64_t n_cells, const unsigned long long *key,
                               const unsigned long long *time, int8_t *s, double *t,
                               uint32_t *n, unsigned long long *sums)
@@ -704,6 +715,15 @@ hipError_t launch_pack(uint64_t n_cells, const int8_t *s, const double *t,
     const unsigned block = 256;
     hipLaunchKernelGGL(pack_kernel, dim3(reduce_grid(n_cells, block)), dim3(block), 0, stream,
                        n_cells, s, t, n, key, time, sum_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_bound(uint64_t n_cells, const uint32_t *n, unsigned long long *flag,
+                              hipStream_t stream)
+{
+    const unsigned block = 256;
+    hipLaunchKernelGGL(count_bound_kernel, dim3(reduce_grid(n_cells, block)), dim3(block), 0,
+                       stream, n_cells, n, flag);
     return hipGetLastError();
 }
 

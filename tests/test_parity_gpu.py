@@ -158,22 +158,63 @@ def test_resume_from_checkpoint(torch):
     b.close()
 
 
-def test_arbitrary_state_and_exact_ties(torch):
+TIE_CASES = {
+    # one tile spans the lattice: the spanning-tile visit
+    "spanning": (workloads.lattice(2, (33, 31), 0.7, "glauber", h=0.1, seed=23), None, 12.0),
+    # cut into region tiles: the scan applies the index rule, re-tests
+    # postpone tied cells to the next visit
+    "region2d": (workloads.lattice(2, (150, 130), 0.7, "glauber", h=0.1, seed=25),
+                 dict(tile=(32, 32), ghost=(4, 4)), 12.0),
+    "region3d": (workloads.lattice(3, (40, 36, 30), 0.3, "metropolis", h=0.1, seed=26),
+                 dict(tile=(12, 12, 12), ghost=(1, 1, 1)), 5.0),
+    # the same through the persistent batch kernel
+    "batch": (workloads.lattice(2, (140, 120), 0.5, "glauber", seed=27), None, 10.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(TIE_CASES))
+def test_arbitrary_state_and_exact_ties(torch, case):
     """From a hand-made state -- every time equal (ties everywhere), large
-    counts -- the GPU must follow the oracle's (time, index) order."""
-    params = workloads.lattice(2, (33, 31), 0.7, "glauber", h=0.1, seed=23)
+    counts (up to just below the 2^31 bound) -- the GPU must follow the
+    oracle's (time, index) order."""
+    params, tuning, T = TIE_CASES[case]
+    print(f"ties {case}: {params} {tuning} T={T}", file=sys.stderr, flush=True)
     s, t, n = oracle.init(params)
     t[:] = 0.5
-    n[:] = np.arange(n.size, dtype=np.uint32) * 7919 + 4_000_000_000 % 2**32
+    n[:] = (np.arange(n.size, dtype=np.uint64) * 7919) % 600_000_000 + 1_500_000_000
     s1, t1, n1 = s.copy(), t.copy(), n.copy()
-    oracle.run(params, 12.0, s1, t1, n1)
-    lat = aca.Lattice(params)
+    oracle.run(params, T, s1, t1, n1)
+    lat = aca.Lattice(params, tuning=tuning)
     lat.spins.copy_(torch.from_numpy(s))
     lat.times.copy_(torch.from_numpy(t))
     lat.counts.copy_(torch.from_numpy(n.view(np.int32)))
     lat.resume(0.0)
-    lat.advance(12.0)
+    if case == "batch":
+        b = aca.Batch(1)
+        b.advance([lat], [T])
+        b.close()
+    else:
+        lat.advance(T)
     assert_same_state(lat.read(), (s1, t1, n1), "ties")
+    lat.close()
+
+
+def test_resume_refuses_counts_at_2_31(torch):
+    """Counts are 31-bit (the region visits keep a claim in bit 31): resume
+    must refuse a restored count of 2^31, leaving the lattice as it was, and
+    accept 2^31 - 1."""
+    params = workloads.lattice(2, (96, 80), 0.3, seed=28)
+    lat = aca.Lattice(params).init()
+    s, t, n = lat.read()
+    n[1234] = 2**31
+    lat.counts.copy_(torch.from_numpy(n.view(np.int32)))
+    with pytest.raises(aca.AcaError) as e:
+        lat.resume(0.0)
+    assert e.value.code == aca.ACA_EINVAL and "2^31" in str(e.value)
+    assert lat.stats()["last_T"] == 0.0        # still the initialised lattice
+    n[1234] = 2**31 - 1
+    lat.counts.copy_(torch.from_numpy(n.view(np.int32)))
+    lat.resume(0.0)
     lat.close()
 
 
