@@ -75,7 +75,16 @@ __device__ __forceinline__ double neg_log_u53(uint64_t w)
     }
     const double num = f - 1.0;
     const double den = f + 1.0;
-    const double s = num / den;
+    // s = num / den, the IEEE quotient, by the hardware's division sequence
+    // (reciprocal, two Newton steps, one fused correction) without its
+    // operand scaling and special-value fix-up: here den is in [1.70, 2.42]
+    // and num is 0 or at least 2^-53 in magnitude, so neither step changes
+    // anything and the result is bit for bit the compiler's num / den.
+    double r = __builtin_amdgcn_rcp(den);
+    r = __builtin_fma(__builtin_fma(-den, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-den, r, 1.0), r, r);
+    const double q0 = num * r;
+    const double s = __builtin_fma(__builtin_fma(-den, q0, num), r, q0);
     const double z = s * s;
     double p = 1.0 / 21.0;
     p = p * z; p = p + 1.0 / 19.0;
@@ -87,9 +96,9 @@ __device__ __forceinline__ double neg_log_u53(uint64_t w)
     p = p * z; p = p + 1.0 / 7.0;
     p = p * z; p = p + 1.0 / 5.0;
     p = p * z; p = p + 1.0 / 3.0;
-    double r = z * p;
-    r = s * r;
-    double lf = s + r;
+    double t = z * p;
+    t = s * t;
+    double lf = s + t;
     lf = lf + lf;
     const double ed = (double)e;
     const double head = ed * kLn2Head;

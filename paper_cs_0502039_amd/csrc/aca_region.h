@@ -630,6 +630,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             }
             int bi = 0, q[3] = {0, 0, 0};
             uint64_t W[K];
+            // least of the horizon and the applied cell's neighbour times:
+            // they cannot change while the cell is listed, so its own re-test
+            // can use the value taken before the arrival is applied
+            double own_tmin = 0.0;
             if (active) {
                 bi = lcur[start + lane];
                 const int row = (int)__umulhi((uint32_t)bi, magic1);   // q1 + pitch1 q2
@@ -644,6 +648,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 // its arrival (no neighbour can be enabled meanwhile)
 #pragma unroll
                 for (int k = 0; k <= Z; ++k) W[k] = ldw(&ts[bi + off(k)]);
+                own_tmin = horizon_t;
+#pragma unroll
+                for (int k = 1; k <= Z; ++k) own_tmin = __builtin_fmin(own_tmin, time_of(W[k]));
                 // (sum of neighbour spins + Z) / 2 = Z - (number of -1 neighbours)
                 int neg = 0;
 #pragma unroll
@@ -709,11 +716,11 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             for (int s = 0; s <= Z; ++s) {
                 // a ring neighbour is tested too; its claim never succeeds
                 const double tc = time_of(W[s]);
-                double tmin = s == 0 ? horizon_t : pre[s];
+                double tmin = s == 0 ? own_tmin : pre[s];
 #pragma unroll
                 for (int j = 0; j < Z; ++j) {
                     const int k = S.nb[s][j];
-                    if (s == 0 || (k != 0 && k != S.lead[s]))
+                    if (s > 0 && k != 0 && k != S.lead[s])
                         tmin = __builtin_fmin(tmin, time_of(W[k]));
                 }
                 want[s] = active && tc < tmin;
