@@ -40,10 +40,11 @@ HBM_PEAK_GBS = 8000.0
 # instruction every 4 cycles per SIMD; binary64 add/mul run at this rate).
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # Issue slots one applied arrival needs at minimum on gfx950: Philox4x32-10 is
-# 20 v_mad_u64_u32 (half rate, 2 slots each) and 20 v_bitop3_b32; -ln u is 51
-# binary64 slots (16 mul, 16 add, the division sequence with its quarter-rate
-# reciprocal, conversions) and 11 integer ones; flip test and clock update 8.
-SLOTS_PER_EVENT = 40 + 20 + 51 + 11 + 8
+# 20 v_mad_u64_u32 (half rate, 2 slots each) and 20 v_bitop3_b32; -ln u is 48
+# binary64 slots (16 mul, 16 add, the quotient's reciprocal -- quarter rate --
+# with its Newton steps and correction, conversions) and 11 integer ones; flip
+# test and clock update 8.
+SLOTS_PER_EVENT = 40 + 20 + 48 + 11 + 8
 
 
 def log(msg: str) -> None:
