@@ -21,9 +21,11 @@
 //    neighbourhood once -- 13 words in 2D, 25 in 3D (the cell, its 2*dim
 //    neighbours, the cells two steps away and the diagonals) -- and re-tests
 //    the cell and its neighbours from those registers;
-//  * the enabling test compares times strictly; only when a candidate's time
-//    equals a neighbour's (rare in binary64) does the wavefront take the path
-//    that resolves the tie by global index;
+//  * the initial scan of a visit applies the exact (time, global index)
+//    order, taking the index path only when a cell's time equals a
+//    neighbour's (rare in binary64); the re-test after an arrival is strict
+//    and leaves such a tied cell to the next visit's scan (postponing an
+//    enabled arrival never changes the trajectory);
 //  * the newly enabled cells of a wavefront are appended with one LDS atomic;
 //  * a worklist never holds two cells that read each other (both could not
 //    be enabled at once, and a listed cell stays enabled until it applies),
