@@ -495,8 +495,8 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     if (own_due) {
     // ---- initial scan: every enabled simulated cell into list 0, US cells
     // per thread per step (their reads issued together, one list atomic per
-    // wavefront for all of them)
-    constexpr int US = 4;
+    // wavefront for all of them; nearest neighbours only)
+    constexpr int US = Q == 1 ? 4 : 1;   // a wider reach has no registers to spare
     for (int base = tid - lane; base < boxp; base += US * nthreads) {
         bool en[US];
         int cell[US];
@@ -779,10 +779,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // atomic (reads, stores and atomics complete in order on one counter, so a
     // read issued after atomics waits for them) and keeps only the keys: the
     // cells' indices and flags are computed again, from an index the compiler
-    // cannot see through, when the keys are used.  12 cells per thread cover
-    // a whole region in one step at the default tiles (4884 box cells for 512
-    // threads in 2D, 9216 for 1024 in 3D).
-    constexpr int UM = 12;
+    // cannot see through, when the keys are used.  For nearest neighbours, 12
+    // cells per thread cover a whole region in one step at the default tiles
+    // (4884 box cells for 512 threads in 2D, 9216 for 1024 in 3D).
+    constexpr int UM = Q == 1 ? 12 : 4;   // a wider reach has no registers to spare
     auto opaque = [](int v) {
         __asm__("" : "+v"(v));
         return v;
