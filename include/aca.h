@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define ACA_ABI_VERSION 2u
+#define ACA_ABI_VERSION 3u
 
 typedef int32_t aca_status;
 enum {
@@ -114,31 +114,71 @@ typedef struct aca_stats {
     uint64_t region_bytes;  /* bytes the visit kernels must move: 16 B per
                                region cell in, 16 B per owned cell out,
                                summed over launches */
+    /* Efficiency instruments after Section 4, whose efficiency at an
+     * iteration of Fig. 3.2 is N0 / N, the fraction of cells passing the
+     * enabling test (Step 2).  Summed over tile visits:
+     *  scan_enabled / scan_live: of the owned cells with an arrival before
+     *    the horizon when a visit loaded them, the fraction the visit's
+     *    initial scan found enabled (at the first launch from a fresh state
+     *    this is exactly the first iteration of Fig. 3.2);
+     *  (events + ghost_events) / round_cells: arrivals applied per simulated
+     *    cell per worklist round -- each round applies exactly the cells that
+     *    pass the test, so this is N0 / N of Fig. 3.2 inside the regions. */
+    uint64_t scan_live;
+    uint64_t scan_enabled;
+    uint64_t round_cells;   /* simulated cells before the launch's horizon at
+                               load, times the rounds the visit ran */
 } aca_stats;
+
+/* One record per visit launch of the last aca_advance (see aca_get_trace). */
+typedef struct aca_launch_record {
+    uint64_t events;        /* arrivals applied to owned cells */
+    uint64_t ghost_events;  /* arrivals applied to ghost copies */
+    uint64_t scan_live;     /* as in aca_stats, for this launch */
+    uint64_t scan_enabled;
+    uint64_t round_cells;
+    uint64_t live_tiles;    /* tiles with an owned arrival still due afterwards */
+    double kernel_ms;       /* HIP-event time of the launch */
+} aca_launch_record;
 
 typedef struct aca_lattice aca_lattice;   /* opaque host handle */
 
 uint32_t aca_abi_version(void);
 const char *aca_last_error(void);
 
-/* Flip thresholds thr[idx] = floor(p * 2^32) (2^32 when p >= 1), idx =
- * (sum + z)/2 + (z+1)(s+1)/2 with z = 2 dim neighbour slots (or the
- * q-th degree neighbourhood's size - 1), for the probability table of the
- * appendix program.  Host only, needs no GPU.  out must hold cap >= 2(z+1)
- * entries; *count receives 2(z+1). */
+/* Flip thresholds of parameters p, without a lattice handle.  Section 2,
+ * Eq. (1): the new state is drawn from a distribution fixed by the cell's
+ * state and its neighbours'; for the Ising rule this is the probability
+ * table of the appendix program (Glauber x/(1+x), x = exp(-beta dE)) or the
+ * Metropolis min(1, exp(-beta dE)), dE = 2 s (J sum + h).  Entry idx =
+ * (sum + z)/2 + (z+1)(s+1)/2 -- the appendix's index generalised to z = 2 dim
+ * neighbour slots (or the q-th degree neighbourhood's size - 1) -- holds
+ * floor(p 2^32), or 2^32 when p >= 1; an arrival flips the spin iff its
+ * 32-bit draw is below the entry.  Host only, needs no GPU.  out (host) must
+ * hold cap >= 2(z+1) entries; *count (may be NULL) receives 2(z+1).
+ * ACA_EINVAL for invalid p, a NULL out or a short cap; nothing is written
+ * then. */
 aca_status aca_thresholds(const aca_params *p, uint64_t *out, int32_t cap,
                           int32_t *count);
 
 /* Sizes for p: number of cells, and bytes of device scratch the caller must
  * provide to aca_create (two working snapshots of 16 bytes per cell, a byte
- * per cell for per-tile flags, and counters: about 33 N + 512 bytes). */
+ * per cell for per-tile flags, and counters: about 33 N + 512 bytes).
+ * The array of cells and its neighbourhood map are those of Section 2 (a
+ * periodic box, neighbours one step along each axis).  ACA_EINVAL for
+ * invalid p; either output pointer may be NULL. */
 aca_status aca_query(const aca_params *p, uint64_t *n_cells,
                      uint64_t *scratch_bytes);
 
 /* Create a handle over caller-owned device buffers: spins int8[N], times
  * double[N], counts uint32[N] (structure of arrays, index as above), all
  * 256-byte aligned, and scratch of scratch_bytes >= aca_query's value.
- * The handle owns none of them.  No device work is done. */
+ * These are the per-cell state s(c), local time t(c) and arrival count n(c)
+ * of Fig. 3.1 (Section 3; the count numbers the draws of Eq. (5)).  The
+ * handle owns none of them.  No device work is done.  The scratch buffer is
+ * an addition to the paper's state: it holds the two working snapshots the
+ * launches alternate between.  ACA_EINVAL for invalid p, NULL or misaligned
+ * buffers; ACA_ENOMEM when scratch_bytes is short; *out is then untouched. */
 aca_status aca_create(const aca_params *p, int8_t *d_spin, double *d_time,
                       uint32_t *d_count, void *d_scratch, uint64_t scratch_bytes,
                       aca_lattice **out);
@@ -148,7 +188,10 @@ aca_status aca_set_tuning(aca_lattice *lat, const aca_tuning *t);
 aca_status aca_get_tuning(const aca_lattice *lat, aca_tuning *out);
 
 /* Initial state (asynchronous on `stream`): each cell's first arrival is one
- * exponential gap after time 0, its spin set per `init`, its count 0. */
+ * exponential gap after time 0 (the Poisson stream of Section 1 starts at
+ * time 0; the gap is Eq. (5)'s -ln r / lambda with the cell's initial draw),
+ * its spin set per `init`, its count 0.  ACA_ESTATE for a batch member,
+ * ACA_EDEVICE if the launch fails. */
 aca_status aca_init(aca_lattice *lat, void *stream);
 
 /* Declare that the state buffers already hold a state advanced to horizon
@@ -158,7 +201,11 @@ aca_status aca_init(aca_lattice *lat, void *stream);
  * returns ACA_EINVAL, leaving the lattice as it was, if one is not. */
 aca_status aca_resume(aca_lattice *lat, double T_done);
 
-/* Apply every arrival with time < T, in the conservative parallel schedule.
+/* Apply every arrival with time < T, in the conservative parallel schedule:
+ * the loop of Fig. 3.1 run until every local time reaches end_time = T, a
+ * cell applying its arrival once no neighbour's pending arrival precedes it
+ * (ties by cell index), its new state drawn per Eq. (1)-(2) and its next
+ * arrival set by Eq. (5); aggregated into workgroup tiles as in Fig. 3.3/3.4.
  * Returns when done (the state is in the caller's buffers and the stream is
  * synchronised).  T must be finite and >= the last horizon (equal: no-op),
  * and rate * T <= 2^30 (ACA_EINVAL otherwise: counts are kept below 2^31;
@@ -184,7 +231,22 @@ aca_status aca_advance_frames(aca_lattice *lat, double T, double dt, int8_t *d_f
  * change, only the parallelism per launch. */
 aca_status aca_set_lag(aca_lattice *lat, double lag);
 
+/* Counters since aca_init (or aca_resume); see aca_stats. */
 aca_status aca_get_stats(const aca_lattice *lat, aca_stats *out);
+
+/* The flip thresholds the lattice applies (as aca_thresholds for its
+ * parameters; Section 2, Eq. (1), and the appendix's probability table).
+ * out (host) must hold n >= 2(z+1) entries; ACA_EINVAL otherwise. */
+aca_status aca_get_thresholds(const aca_lattice *lat, uint64_t *out, int32_t n);
+
+/* Per-launch records of the last aca_advance (or aca_advance_frames), in
+ * launch order: the efficiency of each iteration, in the sense of Section 4,
+ * as the advance went.  Up to cap records are copied to out (host); *count
+ * receives the number held (at most ACA_TRACE_MAX: the first launches of a
+ * longer advance). */
+#define ACA_TRACE_MAX 65536
+aca_status aca_get_trace(const aca_lattice *lat, aca_launch_record *out, int32_t cap,
+                         int32_t *count);
 
 /* Autotuning on the caller's own work.  Every schedule yields the same
  * trajectory (Fig. 3.4's partition invariance), so the tuner advances the
@@ -201,7 +263,9 @@ aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_t n, double
                     void *stream, int32_t *best, double *rates, int32_t *n_out);
 
 
-/* Synchronous copy of the state to host memory (any pointer may be NULL). */
+/* Synchronous copy of the state -- the spins, local times and arrival
+ * counts of Section 3's per-cell variables -- to host memory (any pointer may
+ * be NULL; each must hold N elements).  ACA_ESTATE for a batch member. */
 aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
                     uint32_t *h_count, void *stream);
 

@@ -30,7 +30,7 @@ EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_server_step", "aca_server_job", "aca_server_read", "aca_server_release",
             "aca_server_load", "aca_server_get_stats", "aca_server_destroy", "aca_tune",
             "aca_batch_tune", "aca_batch_set_order", "aca_server_set_order",
-            "aca_advance_frames", "aca_set_lag")
+            "aca_advance_frames", "aca_set_lag", "aca_get_thresholds", "aca_get_trace")
 ORDER_WORK, ORDER_ARRIVAL = 0, 1
 TUNE_MAX = 16
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -67,7 +67,18 @@ class Stats(ctypes.Structure):
                 ("flips", ctypes.c_uint64), ("ghost_events", ctypes.c_uint64),
                 ("cell_checks", ctypes.c_uint64), ("last_T", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
-                ("region_bytes", ctypes.c_uint64)]
+                ("region_bytes", ctypes.c_uint64), ("scan_live", ctypes.c_uint64),
+                ("scan_enabled", ctypes.c_uint64), ("round_cells", ctypes.c_uint64)]
+
+
+class LaunchRecord(ctypes.Structure):
+    _fields_ = [("events", ctypes.c_uint64), ("ghost_events", ctypes.c_uint64),
+                ("scan_live", ctypes.c_uint64), ("scan_enabled", ctypes.c_uint64),
+                ("round_cells", ctypes.c_uint64), ("live_tiles", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double)]
+
+
+TRACE_MAX = 65536
 
 
 class BatchStats(ctypes.Structure):
@@ -135,6 +146,8 @@ def load() -> ctypes.CDLL:
         "aca_batch_set_order": [P, i32],
         "aca_advance_frames": [P, f64, f64, P, ctypes.c_int64, ctypes.c_int64, P],
         "aca_set_lag": [P, f64],
+        "aca_get_thresholds": [P, P, i32],
+        "aca_get_trace": [P, ctypes.POINTER(LaunchRecord), i32, P],
         "aca_server_set_order": [P, i32],
         "aca_batch_tune": [P, P, P, i32, i32, pt, i32, f64, P, P, P, P],
         "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
@@ -299,6 +312,21 @@ class Lattice:
         st.struct_size = ctypes.sizeof(Stats)
         _check(self.lib.aca_get_stats(self._h, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in Stats._fields_ if k not in ("struct_size", "pad_")}
+
+    def thresholds(self) -> np.ndarray:
+        """The flip thresholds this lattice applies."""
+        out = np.zeros(64, dtype=np.uint64)
+        _check(self.lib.aca_get_thresholds(self._h, out.ctypes.data, 64))
+        return out[: thresholds(self.params).size].copy()
+
+    def trace(self) -> list[dict]:
+        """Per-launch records of the last advance (efficiency per launch)."""
+        count = ctypes.c_int32(0)
+        _check(self.lib.aca_get_trace(self._h, None, 0, ctypes.byref(count)))
+        buf = (LaunchRecord * max(1, count.value))()
+        _check(self.lib.aca_get_trace(self._h, buf, count.value, ctypes.byref(count)))
+        return [{k: getattr(buf[i], k) for k, _ in LaunchRecord._fields_}
+                for i in range(count.value)]
 
     def read(self) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
         """Synchronous copy of (spins int8, times float64, counts uint32) to the host."""

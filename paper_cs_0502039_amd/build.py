@@ -3,10 +3,12 @@
 Every floating-point operation of the arrival-time recipe must round on its own,
 so device and host code are compiled with -ffp-contract=off and no reassociation
 (-fno-fast-math); packed FP32 instructions are disabled.  -fno-honor-nans is the
-one relaxation: no value the library computes can be a NaN (times are finite
-and positive, u lies in (0, 1), every divisor is at least 1), and the flag lets
-the compiler drop the NaN-quieting it would otherwise put in front of every
-binary64 min in the enabling tests; it allows no other change to any result.
+one relaxation, and it applies to device code only: no value a kernel computes
+can be a NaN (times are finite and positive, u lies in (0, 1), every divisor is
+at least 1), and the flag lets the compiler drop the NaN-quieting it would
+otherwise put in front of every binary64 min in the enabling tests; it allows
+no other change to any result.  Host code keeps IEEE NaN semantics, because it
+validates caller arguments that may well be NaN.
 """
 from __future__ import annotations
 
@@ -32,7 +34,8 @@ def hipcc() -> str:
 
 def build_command(out: str, extra=()) -> list[str]:
     return [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
-            "-ffp-contract=off", "-fno-fast-math", "-fno-honor-nans", "-fvisibility=hidden",
+            "-ffp-contract=off", "-fno-fast-math", "-Xarch_device", "-fno-honor-nans",
+            "-fvisibility=hidden",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"),
             *[os.path.join(CSRC, s) for s in SOURCES], "-o", out, *extra]

@@ -61,7 +61,14 @@ ScratchLayout scratch_layout(uint64_t n)
     return l;
 }
 
-bool is_finite(double v) { return std::isfinite(v); }
+// Decided on the bit pattern (exponent field not all ones), so the check holds
+// whatever floating-point assumptions the compiler is given.
+bool is_finite(double v)
+{
+    uint64_t bits;
+    memcpy(&bits, &v, sizeof bits);
+    return (bits & 0x7FF0000000000000ull) != 0x7FF0000000000000ull;
+}
 
 int ball_size(int dim, int q)
 {
@@ -126,6 +133,7 @@ aca_status check_params(const aca_params *in, uint64_t *n_out, aca_params *full)
 int build_thresholds(const aca_params *p, uint64_t *thr)
 {
     const int z = p->range > 1 ? ball_size(p->dim, p->range) : 2 * p->dim;
+    if (!thr) return 2 * (z + 1);
     for (int spin = -1; spin <= 1; spin += 2) {
         for (int sum = -z; sum <= z; sum += 2) {
             const double js = p->J * (double)sum;
@@ -627,6 +635,7 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
     HIP_TRY(hipMemsetAsync(lat->time[1], 0, 8 * lat->n, s));
 
     HIP_TRY(hipMemsetAsync(lat->dead, 0, tiles, s));
+    lat->trace.clear();
 
     // Launch k reads snapshot k % 2, merges into the other one and counts
     // into slot k % 2; its last block publishes the slot to pinned host
@@ -650,16 +659,14 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
         HIP_TRY(hipEventRecord(lat->ev_stop[slot], s));
         return ACA_OK;
     };
-    // Every launch applies at least the globally earliest due arrival, so the
-    // loop ends; the bound only turns a pathological schedule into an error.
-    const uint64_t max_launches = 100000;
+    // Every launch applies at least the globally earliest due arrival (the
+    // deadlock-freedom argument after Fig. 3.1), and there are finitely many
+    // arrivals before T, so the loop ends however many launches that takes.
+    // The only watchdog is the check below that a launch applied something.
     aca_status est = enqueue(0);
     if (est != ACA_OK) return est;
     uint64_t enqueued = 1, prev_live = tiles, k = 0, idle = 0;
     for (;; ++k) {
-        if (k + 1 >= max_launches)
-            return fail(ACA_ENOPROGRESS, "horizon not reached after %llu launches",
-                        (unsigned long long)k + 1);
         if (!lagged && enqueued == k + 1 && prev_live * 8 > tiles) {
             est = enqueue(k + 1);
             if (est != ACA_OK) return est;
@@ -678,6 +685,13 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
         S.ghost_events += hc[aca::kGhostEvents];
         S.sweeps += hc[aca::kSweeps];
         S.cell_checks += hc[aca::kChecks];
+        S.scan_live += hc[aca::kScanLive];
+        S.scan_enabled += hc[aca::kScanEnabled];
+        S.round_cells += hc[aca::kRoundCells];
+        if (lat->trace.size() < ACA_TRACE_MAX)
+            lat->trace.push_back(aca_launch_record{
+                hc[aca::kEvents], hc[aca::kGhostEvents], hc[aca::kScanLive],
+                hc[aca::kScanEnabled], hc[aca::kRoundCells], hc[aca::kLiveTiles], (double)kms});
         if (hc[aca::kLiveTiles] == 0) break;
         // under a lag bound one launch may find nothing before its horizon
         // (the least pending time it was set from was stale); the next one
@@ -774,6 +788,27 @@ ACA_EXPORT aca_status aca_get_stats(const aca_lattice *lat, aca_stats *out)
 {
     if (!lat || !out) return fail(ACA_EINVAL, "NULL argument");
     *out = lat->stats;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_get_thresholds(const aca_lattice *lat, uint64_t *out, int32_t n)
+{
+    if (!lat || !out) return fail(ACA_EINVAL, "NULL argument");
+    const int need = build_thresholds(&lat->p, nullptr);
+    if (n < need) return fail(ACA_EINVAL, "n %d < %d entries", n, need);
+    memcpy(out, lat->thr, sizeof(uint64_t) * need);
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_get_trace(const aca_lattice *lat, aca_launch_record *out, int32_t cap,
+                                    int32_t *count)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (cap > 0 && !out) return fail(ACA_EINVAL, "out is NULL");
+    const size_t held = lat->trace.size();
+    const size_t copy = cap > 0 ? std::min(held, (size_t)cap) : 0;
+    if (copy) memcpy(out, lat->trace.data(), copy * sizeof(aca_launch_record));
+    if (count) *count = (int32_t)held;
     return ACA_OK;
 }
 

@@ -328,6 +328,9 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
                 atomicAdd(&st.ctr[kGhostEvents], (unsigned long long)r.ghost);
                 atomicAdd(&st.ctr[kChecks], (unsigned long long)r.checks);
                 atomicAdd(&st.ctr[kSweeps], (unsigned long long)r.rounds);
+                atomicAdd(&st.ctr[kScanLive], (unsigned long long)r.scan_live);
+                atomicAdd(&st.ctr[kScanEnabled], (unsigned long long)r.scan_enabled);
+                atomicAdd(&st.ctr[kRoundCells], (unsigned long long)r.round_cells);
                 atomicAdd(&st.epoch_moves, (unsigned long long)(r.events + r.ghost));
                 if (r.any_live) atomicAdd(&st.live, 1u);
                 // a later epoch's visit of this tile may run on another XCD

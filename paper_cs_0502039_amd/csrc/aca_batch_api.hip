@@ -376,7 +376,7 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
                                      void *stream, int32_t *n_members)
 {
     if (!b) return fail(ACA_EINVAL, "batch is NULL");
-    if (!std::isfinite(budget_ms)) return fail(ACA_EINVAL, "budget_ms must be finite");
+    if (!is_finite(budget_ms)) return fail(ACA_EINVAL, "budget_ms must be finite");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const auto t0 = std::chrono::steady_clock::now();
     // member lists: priority order (most remaining work first), joining, all
@@ -485,6 +485,9 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
             L.sweeps += st.ctr[aca::kSweeps];
             L.ghost_events += st.ctr[aca::kGhostEvents];
             L.cell_checks += st.ctr[aca::kChecks];
+            L.scan_live += st.ctr[aca::kScanLive];
+            L.scan_enabled += st.ctr[aca::kScanEnabled];
+            L.round_cells += st.ctr[aca::kRoundCells];
             L.events += events;
             L.flips += st.sum_flips;
             L.region_bytes += (uint64_t)st.total_epochs * m.region_bytes;

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/aca.h"
 #include "aca_internal.h"
@@ -46,16 +47,19 @@ ScratchLayout scratch_layout(uint64_t n);
 // Counter words in scratch: two slots of visit counters (launches alternate
 // between them), the pack/unpack sums, and the two slots' block tickets.
 enum : int {
-    kSlotWords = 8, kSumStart = 16, kSumEnd = 17, kSumFlips = 18, kTicketWord = 20,
-    kCounterWords = 24
+    kSlotWords = 16, kSumStart = 32, kSumEnd = 33, kSumFlips = 34, kTicketWord = 36,
+    kCounterWords = 40
 };
+static_assert(aca::kNumCounters <= kSlotWords, "a counter slot holds every counter");
+static_assert(8 * kCounterWords <= 2 * kAlign, "counters fit their scratch block");
 
 bool is_finite(double v);
 // Validates the caller's parameters (either ABI size) and writes a full copy
 // (range 1 for the older size) to *full when full is not NULL.
 aca_status check_params(const aca_params *p, uint64_t *n_out, aca_params *full);
 // Fills the flip table for z neighbours (2 dim, or the q-th degree
-// neighbourhood's size - 1); returns its 2 (z + 1) entries.
+// neighbourhood's size - 1); returns its 2 (z + 1) entries (thr NULL: only
+// counts them).
 int build_thresholds(const aca_params *p, uint64_t *thr);
 // Cells at lattice distance 1..q (the q-th degree neighbourhood without c).
 int ball_size(int dim, int q);
@@ -95,6 +99,7 @@ struct aca_lattice {
     unsigned long long *host_ctr_dev;   // its device address
     bool attached;                  // member of a batch: advanced by it only
     double lag;                     // lag bound (0: none)
+    std::vector<aca_launch_record> trace;   // launches of the last advance
 };
 
 namespace aca_host {

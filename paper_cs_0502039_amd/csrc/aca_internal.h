@@ -18,7 +18,12 @@ enum Counter : int {
     kSweeps = 4,        // worklist rounds summed over tile visits
     kChecks = 5,        // enabling tests evaluated
     kTminBits = 6,      // least pending time of the owned cells at load (bits)
-    kNumCounters = 8
+    // Efficiency instruments (Section 4: the fraction of cells that pass the
+    // enabling test at an iteration of Fig. 3.2, N0 / N)
+    kScanLive = 7,      // owned cells with an arrival before the horizon at load
+    kScanEnabled = 8,   // of which the visit's initial scan found enabled
+    kRoundCells = 9,    // simulated cells before the horizon at load, times rounds run
+    kNumCounters = 12
 };
 
 // Working state of a cell during aca_advance, two 64-bit words:

@@ -319,6 +319,9 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     __syncthreads();
     bool due = false;
     uint64_t tmin_own = ~0ull;
+    // owned and simulated cells before the horizon at load (Section 4's
+    // efficiency instruments), counted by lane 0 of each wavefront
+    uint32_t cnt_own_live = 0, cnt_inner_live = 0;
     for (int j = tid; j < R.box; j += nthreads) {
         int q[3];
         q[0] = j % rbox[0];
@@ -339,18 +342,22 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         const unsigned long long key = a.key_in[gi];
         const unsigned long long tb = a.time_in[gi];
         ts[j] = (uint64_t)tb | ((key & 1ull) << 63);
+        bool own_cell = in_core;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            own_cell = own_cell && pi[d] >= R.olo[d] && pi[d] < R.ohi[d];
         if (in_core) {
             const int ii = R.inner_index(pi);
             nl[ii] = (uint32_t)(key >> 32);
             fl[ii] = 0;
-            bool own_cell = true;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d)
-                own_cell = own_cell && pi[d] >= R.olo[d] && pi[d] < R.ohi[d];
             due = due || (own_cell && (uint64_t)tb < a.final_bits);
             if (own_cell && (uint64_t)tb < tmin_own) tmin_own = (uint64_t)tb;
         }
+        cnt_own_live += (uint32_t)__popcll(__ballot(own_cell && (uint64_t)tb < a.final_bits));
+        cnt_inner_live += (uint32_t)__popcll(__ballot(in_core && (uint64_t)tb < a.horizon_bits));
     }
+    if (lane == 0 && cnt_own_live) atomicAdd(&ctr[10], (int)cnt_own_live);
+    if (lane == 0 && cnt_inner_live) atomicAdd(&ctr[12], (int)cnt_inner_live);
     if (a.track_tmin && tmin_own != ~0ull) atomicMin(&tmin_block, tmin_own);
     const int own_due = __syncthreads_or(due ? 1 : 0);
     if (a.track_tmin && tid == 0 && tmin_block != ~0ull)
@@ -369,20 +376,26 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
     if (own_due) {
     // ---- initial scan: every enabled cell, claimed, into list 0.  A
     // wavefront's 64 lanes test 64 consecutive cells, i.e. two claim words.
+    uint32_t cnt_scan_own = 0;   // owned cells listed (lane 0 of each wavefront)
     for (int base = tid - lane; base < R.inner; base += nthreads) {
         const int i = base + lane;
-        bool en = false;
+        bool en = false, owned = false;
         if (i < R.inner) {
             int p[3];
             R.coords(i, p);
             en = cell_enabled<DIM>(R, ts, p, R.box_index(p), horizon);
             ++my_checks;
+            owned = true;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) owned = owned && p[d] >= R.olo[d] && p[d] < R.ohi[d];
         }
         const uint64_t m = __ballot(en);
+        cnt_scan_own += (uint32_t)__popcll(__ballot(en && owned));
         if (lane == 0 && (uint32_t)m) claim[base >> 5] = (uint32_t)m;
         if (lane == 1 && (uint32_t)(m >> 32)) claim[(base >> 5) + 1] = (uint32_t)(m >> 32);
         wave_append(en, (uint16_t)i, lists, &sizes[0], lane);
     }
+    if (lane == 0 && cnt_scan_own) atomicAdd(&ctr[11], (int)cnt_scan_own);
     __syncthreads();
 
     // ---- rounds: apply every listed arrival; re-test the cells whose
@@ -525,6 +538,9 @@ __global__ void __launch_bounds__(1024) visit_kernel(VisitArgs a)
         atomicAdd(&gc[kGhostEvents], (unsigned long long)(unsigned)ctr[8]);
         atomicAdd(&gc[kChecks], (unsigned long long)(unsigned)ctr[9]);
         atomicAdd(&gc[kSweeps], (unsigned long long)rounds);
+        atomicAdd(&gc[kScanLive], (unsigned long long)(unsigned)ctr[10]);
+        atomicAdd(&gc[kScanEnabled], (unsigned long long)(unsigned)ctr[11]);
+        atomicAdd(&gc[kRoundCells], (unsigned long long)(unsigned)ctr[12] * (unsigned)rounds);
         if (any_live) atomicAdd(&gc[kLiveTiles], 1ull);
         // owned cells that were all at or past the horizon when loaded can
         // never change again: both snapshots now hold them

@@ -58,6 +58,10 @@ struct RegionTally {
     int own_due;          // an owned cell had an arrival before the horizon at load
     int any_live;         // an owned cell still has one after the visit
     int skipped;          // the tile was final in both snapshots: nothing loaded
+    uint32_t scan_live;   // owned cells with an arrival before the horizon at load
+    uint32_t scan_enabled;   // of which the initial scan listed
+    uint64_t round_cells; // simulated cells before this launch's horizon at load, times
+                          // the rounds run (the denominator of the per-round fraction)
 };
 
 constexpr uint64_t kSign = 0x8000000000000000ull;
@@ -274,7 +278,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     const int nthreads = blockDim.x;
 
     // a tile whose owned cells are final in both snapshots has nothing to do
-    if (a.dead[tile]) return RegionTally{0u, 0u, 0u, 0u, 0, 0, 0, 1};
+    if (a.dead[tile]) return RegionTally{0u, 0u, 0u, 0u, 0, 0, 0, 1, 0u, 0u, 0ull};
     // ---- geometry: box coordinates 0..rin+1 (ring at both ends) per axis
     int tc[3];
     {
@@ -384,6 +388,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // cell still has an arrival before the horizon
     bool due = false;
     uint64_t tmin_own = ~0ull;
+    // owned and simulated cells before the horizon, counted by lane 0 of each
+    // wavefront from ballots (lane 0 takes part in every step its wavefront does)
+    uint32_t cnt_own_live = 0, cnt_inner_live = 0;
     for (int j0 = tid; j0 < boxp; j0 += U * nthreads) {
         bool ok[U], inn[U], own[U];
         uint32_t gi[U];
@@ -409,6 +416,13 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            cnt_own_live += (uint32_t)__popcll(
+                __ballot(ok[u] && own[u] && (uint64_t)tb[u] < a.final_bits));
+            cnt_inner_live += (uint32_t)__popcll(
+                __ballot(ok[u] && inn[u] && (uint64_t)tb[u] < a.horizon_bits));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             if (!ok[u]) continue;
             const int bi = j0 + u * nthreads;
             ts[bi] = (uint64_t)tb[u] | ((key[u] & 1ull) << 63);
@@ -423,6 +437,8 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         }
     }
     if (a.track_tmin && tmin_own != ~0ull) atomicMin(tmin_slot, tmin_own);
+    if (lane == 0 && cnt_own_live) atomicAdd(&ctr[10], (int)cnt_own_live);
+    if (lane == 0 && cnt_inner_live) atomicAdd(&ctr[12], (int)cnt_inner_live);
     const int own_due = __syncthreads_or(due ? 1 : 0);
     if (a.track_tmin && tid == 0 && *tmin_slot != ~0ull)
         atomicMin(&a.counters[kTminBits], (unsigned long long)*tmin_slot);
@@ -497,8 +513,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // per thread per step (their reads issued together, one list atomic per
     // wavefront for all of them; nearest neighbours only)
     constexpr int US = Q == 1 ? 4 : 1;   // a wider reach has no registers to spare
+    uint32_t cnt_scan_own = 0;   // owned cells listed (lane 0 of each wavefront)
     for (int base = tid - lane; base < boxp; base += US * nthreads) {
-        bool en[US];
+        bool en[US], owned[US];
         int cell[US];
 #pragma unroll
         for (int u = 0; u < US; ++u) {
@@ -508,6 +525,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             en[u] = false;
             int q[3];
             decode(bi, q);
+            owned[u] = is_own(q);
             if (Q > 1 && j < boxp && is_inner(q)) {
                 const uint64_t wc = ldw(&ts[bi]);
                 bool tie = false;
@@ -541,6 +559,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         for (int u = 0; u < US; ++u) {
             m[u] = __ballot(en[u]);
             total += (int)__popcll(m[u]);
+            cnt_scan_own += (uint32_t)__popcll(__ballot(en[u] && owned[u]));
         }
         if (total) {
             int b0 = 0;
@@ -553,6 +572,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             }
         }
     }
+    if (lane == 0 && cnt_scan_own) atomicAdd(&ctr[11], (int)cnt_scan_own);
     __syncthreads();
 
     // ---- worklist rounds
@@ -833,7 +853,8 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     atomicAdd(&ctr[9], (int)(my_checks + (Q == 1 ? (uint32_t)(Z + 1) * my_applied : 0u)));
     const int any_live = __syncthreads_or(live ? 1 : 0);
     return RegionTally{(uint32_t)ctr[6], (uint32_t)ctr[7], (uint32_t)ctr[8], (uint32_t)ctr[9],
-                       rounds, own_due, any_live, 0};
+                       rounds, own_due, any_live, 0, (uint32_t)ctr[10], (uint32_t)ctr[11],
+                       (uint64_t)(uint32_t)ctr[12] * (uint64_t)rounds};
 }
 
 }  // namespace region

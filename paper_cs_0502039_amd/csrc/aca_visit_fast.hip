@@ -38,6 +38,9 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
             atomicAdd(&gc[kGhostEvents], (unsigned long long)r.ghost);
             atomicAdd(&gc[kChecks], (unsigned long long)r.checks);
             atomicAdd(&gc[kSweeps], (unsigned long long)r.rounds);
+            atomicAdd(&gc[kScanLive], (unsigned long long)r.scan_live);
+            atomicAdd(&gc[kScanEnabled], (unsigned long long)r.scan_enabled);
+            atomicAdd(&gc[kRoundCells], (unsigned long long)r.round_cells);
             if (r.any_live) atomicAdd(&gc[kLiveTiles], 1ull);
             // owned cells that were all at or past the horizon when loaded can
             // never change again: both snapshots now hold them

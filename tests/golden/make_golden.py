@@ -7,6 +7,10 @@ digests of the final spins (int8), times (float64, little endian) and counts
 
 Usage:  python tests/golden/make_golden.py square_64 square_4096 cubic_256
         python tests/golden/make_golden.py batch_512 --jobs 6
+        python tests/golden/make_golden.py served_16 --jobs 5
+
+``served_16`` holds the first 16 jobs of the served stream at full size (the
+same parameters the serving benchmark submits first), one entry per job id.
 """
 from __future__ import annotations
 
@@ -58,16 +62,20 @@ def main():
     oracle.lib()
     for name in a.names:
         path = os.path.join(HERE, f"{name}.json")
-        if name == "batch_512":
+        if name in ("batch_512", "served_16"):
             from multiprocessing import Pool
-            items = list(enumerate(workloads.batch_512()))
+            if name == "batch_512":
+                items = list(enumerate(workloads.batch_512()))
+            else:
+                items = [(j["id"], {k: v for k, v in j.items() if k not in ("t_arrive", "id")})
+                         for j in workloads.served_stream()[:16]]
             results = [None] * len(items)
             # largest first, so the pool drains evenly
-            order = sorted(items, key=lambda it: -it[1]["L"][0] ** 2 * it[1]["T"])
+            order = sorted(items, key=lambda it: -it[1]["L"][0] ** it[1]["dim"] * it[1]["T"])
             with Pool(a.jobs) as pool:
                 for i, res in pool.imap_unordered(_solve_batch_item, order):
                     results[i] = res
-                    print(f"batch item {i} done ({res['oracle_seconds']} s)", flush=True)
+                    print(f"{name} item {i} done ({res['oracle_seconds']} s)", flush=True)
             doc = {"workload": name, "items": results}
         else:
             params = getattr(workloads, name)()

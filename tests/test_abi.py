@@ -37,7 +37,14 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert aca.abi_version() == 2
+    assert aca.abi_version() == 3
+
+
+def test_struct_layouts_match_the_header():
+    """The binding's structures have the sizes the header's layout gives."""
+    assert ctypes.sizeof(aca.Stats) == 8 + 7 * 8 + 3 * 8 + 8 + 3 * 8
+    assert ctypes.sizeof(aca.LaunchRecord) == 7 * 8
+    assert ctypes.sizeof(aca.Params) == 80
 
 
 def test_params_of_the_first_abi_size_accepted():
@@ -107,6 +114,8 @@ def test_query_sizes():
     dict(dim=0), dict(dim=4), dict(L=[1, 5]), dict(L=[70000, 70000]),
     dict(beta=-0.1), dict(beta=float("nan")), dict(beta=float("inf")),
     dict(rate=0.0), dict(rate=-1.0), dict(J=float("inf")), dict(h=float("nan")),
+    dict(rate=float("nan")), dict(J=float("-inf")), dict(beta=float("-nan")),
+    dict(rate=float("inf")),
 ])
 def test_invalid_params_rejected(bad):
     p = workloads.lattice(2, (8, 8), 0.3)
@@ -127,6 +136,8 @@ def test_struct_size_checked():
 
 def test_null_arguments_rejected():
     lib = aca.load()
+    assert lib.aca_get_thresholds(None, None, 0) == aca.ACA_EINVAL
+    assert lib.aca_get_trace(None, None, 0, None) == aca.ACA_EINVAL
     assert lib.aca_query(None, None, None) == aca.ACA_EINVAL
     assert lib.aca_advance(None, 1.0, None) == aca.ACA_EINVAL
     assert lib.aca_init(None, None) == aca.ACA_EINVAL

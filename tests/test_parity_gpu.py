@@ -451,3 +451,76 @@ def test_range_not_accepted_by_batches_or_server(torch):
     server.close()
     batch.close()
     lat.close()
+
+
+# ------------------------------------------------------------ long horizons
+
+def test_horizon_needing_more_than_100000_launches(torch):
+    """Every horizon the ABI accepts completes: the loop has no launch cap
+    (each launch applies at least the globally earliest due arrival, the
+    deadlock-freedom argument after Fig. 3.1).  One worklist round per visit
+    on a 4x4 torus makes a launch apply only a few arrivals."""
+    params = workloads.lattice(2, (4, 4), 0.45, "glauber", h=0.05, seed=29, T=25000.0)
+    say(f"long horizon {params}")
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    lat = aca.Lattice(params, tuning=dict(max_sweeps=1)).init().advance(params["T"])
+    st = lat.stats()
+    say(f"long horizon: {st['launches']} launches, {st['events']} arrivals")
+    assert st["launches"] > 100000
+    assert_same_state(lat.read(), (s, t, n), "long horizon")
+    assert st["events"] == ev and st["flips"] == fl
+    lat.close()
+
+
+# ------------------------------------------------------------ Section 4 efficiency
+
+EFFICIENCY_CASES = [
+    workloads.square_64(),                                                  # one spanning tile
+    workloads.lattice(2, (200, 131), 0.41, seed=81, T=20.0),               # region tiles
+    workloads.lattice(3, (40, 33, 21), 0.3, "metropolis", h=0.1, seed=82, T=8.0),
+    workloads.lattice(1, (5000,), 0.6, seed=83, T=12.0),
+    workloads.lattice(2, (1024, 1024), 0.44, seed=84, T=5.0),
+]
+
+
+@pytest.mark.parametrize("params", EFFICIENCY_CASES, ids=lambda p: f"{p['dim']}d-{p['L']}")
+def test_first_launch_scan_is_round_one_of_fig_3_2(torch, params):
+    """The first launch's initial scans, over the owned cells, find exactly
+    the cells that pass the enabling test at the first iteration of Fig. 3.2
+    (N0 of Section 4): the cells whose first arrival is before the horizon and
+    precedes every neighbour's, ties by index.  The oracle's synchronous-round
+    schedule counts them independently (arrivals do not depend on spins)."""
+    s, t, n = oracle.init(params)
+    live = int((t < params["T"]).sum())
+    _, rounds, _, rec = oracle.run_rounds(params, params["T"], s.copy(), t.copy(), n.copy(),
+                                          times_only=True, max_record=4)
+    lat = aca.Lattice(params).init().advance(params["T"])
+    tr = lat.trace()
+    st = lat.stats()
+    lat.close()
+    say(f"scan {params['L']}: gpu {tr[0]['scan_enabled']}/{tr[0]['scan_live']} "
+        f"oracle {rec[0]}/{live}; launches {len(tr)}")
+    assert tr[0]["scan_live"] == live
+    assert tr[0]["scan_enabled"] == rec[0]
+    assert len(tr) == st["launches"]
+    # a launch counts the arrivals its regions applied to owned copies and to
+    # ghost copies; the merge may adopt a ghost copy's progress, so the exact
+    # total lies between the two sums
+    own = sum(r["events"] for r in tr)
+    assert own <= st["events"] <= own + sum(r["ghost_events"] for r in tr)
+    assert st["scan_enabled"] == sum(r["scan_enabled"] for r in tr)
+    assert st["round_cells"] > 0 and st["scan_live"] >= live
+    # each worklist round applies exactly the cells that pass the test, so the
+    # per-round fraction lies between 0 and 1/2 (an enabled cell's neighbours
+    # are not enabled)
+    frac = (st["events"] + st["ghost_events"]) / st["round_cells"]
+    assert 0.0 < frac <= 0.5
+
+
+def test_lattice_thresholds_equal_oracle(torch):
+    for p in (workloads.cubic_256(), workloads.square_64(),
+              workloads.lattice(1, (33,), 0.7, "metropolis", h=-0.3, J=0.5)):
+        lat = aca.Lattice(p)
+        want = oracle.thresholds(p["dim"], p["J"], p["h"], p["beta"], p["rule"], 1)
+        assert np.array_equal(lat.thresholds(), want)
+        lat.close()
