@@ -272,6 +272,32 @@ aca_status aca_read(aca_lattice *lat, int8_t *h_spin, double *h_time,
 /* Release the handle (the caller's buffers are untouched). */
 aca_status aca_destroy(aca_lattice *lat);
 
+/* Allocation-free advance, for callers that cannot allocate memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the result of aca_create
+ * + aca_init (or aca_resume(T_done)) + aca_advance(T) over the caller's state
+ * buffers, without a handle, a scratch buffer, pinned host memory or HIP
+ * events.  The working snapshots, tile flags and counters live in a fixed
+ * device array of 64 MiB inside the library (one per device, held until the
+ * process ends), so the lattice may have at most about 2.03 million cells
+ * (33 B of scratch per cell); larger lattices get ACA_EINVAL before any device
+ * work.  The call calls no allocating routine.
+ *  p            lattice parameters (as aca_create)
+ *  d_spin, d_time, d_count
+ *               the caller's state buffers (device, 256-byte aligned, N
+ *               elements each), ready on `stream`
+ *  draw_initial nonzero: first draw the initial state (as aca_init; T_done
+ *               must then be 0); zero: the buffers hold a state advanced to
+ *               T_done (counts below 2^31, else ACA_EINVAL)
+ *  T_done, T    advance from horizon T_done to T >= T_done (rate * T <= 2^30)
+ * Synchronous: returns with the state at T in the buffers.  Every call on a
+ * device shares that device's array (each call clears what must start at
+ * zero), so calls that overlap on one device -- from two host threads, say --
+ * race and must not be made.  Launches run one at a time, each followed by
+ * a copy of its counters to the host. */
+aca_status aca_advance_static(const aca_params *p, int8_t *d_spin, double *d_time,
+                              uint32_t *d_count, int32_t draw_initial, double T_done,
+                              double T, void *stream);
+
 /* Device primitives exposed for element-by-element checks against the
  * oracle (asynchronous on `stream`; all pointers are device pointers).
  *  aca_philox:    out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3]) under key

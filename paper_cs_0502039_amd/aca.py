@@ -30,7 +30,8 @@ EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_server_step", "aca_server_job", "aca_server_read", "aca_server_release",
             "aca_server_load", "aca_server_get_stats", "aca_server_destroy", "aca_tune",
             "aca_batch_tune", "aca_batch_set_order", "aca_server_set_order",
-            "aca_advance_frames", "aca_set_lag", "aca_get_thresholds", "aca_get_trace")
+            "aca_advance_frames", "aca_set_lag", "aca_get_thresholds", "aca_get_trace",
+            "aca_advance_static")
 ORDER_WORK, ORDER_ARRIVAL = 0, 1
 TUNE_MAX = 16
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -148,6 +149,7 @@ def load() -> ctypes.CDLL:
         "aca_set_lag": [P, f64],
         "aca_get_thresholds": [P, P, i32],
         "aca_get_trace": [P, ctypes.POINTER(LaunchRecord), i32, P],
+        "aca_advance_static": [pp, P, P, P, i32, f64, f64, P],
         "aca_server_set_order": [P, i32],
         "aca_batch_tune": [P, P, P, i32, i32, pt, i32, f64, P, P, P, P],
         "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
@@ -602,6 +604,20 @@ def neg_log(words, stream=None):
     _check(load().aca_neg_log(w.data_ptr(), out.data_ptr(), w.numel(),
                               _stream_ptr(torch, stream)))
     return out
+
+
+def advance_static(params: dict, spins, times, counts, T: float, T_done: float = 0.0,
+                   draw_initial: bool = False, stream=None) -> None:
+    """Allocation-free advance of caller tensors (int8, float64, int32 storage
+    holding uint32; N elements each on cuda) from T_done to T, drawing the
+    initial state first when draw_initial is set."""
+    import torch
+    for x, dt in ((spins, torch.int8), (times, torch.float64), (counts, torch.int32)):
+        assert x.dtype == dt and x.is_contiguous() and x.is_cuda
+    _check(load().aca_advance_static(ctypes.byref(make_params(params)), spins.data_ptr(),
+                                     times.data_ptr(), counts.data_ptr(),
+                                     1 if draw_initial else 0, float(T_done), float(T),
+                                     _stream_ptr(torch, stream)))
 
 
 def simulate(params: dict, T: Optional[float] = None, tuning: Optional[dict] = None):

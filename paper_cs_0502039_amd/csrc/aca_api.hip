@@ -21,6 +21,7 @@
 #include <cmath>
 #include <chrono>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "../../include/aca.h"
@@ -596,7 +597,10 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
     if (plan.lds > 64 * 1024)
         HIP_TRY(plan.fast ? aca::set_visit_fast_lds_limit(plan.lds)
                           : aca::set_visit_lds_limit(plan.lds));
-    unsigned long long *host = lat->host_ctr;
+    // counters come back through pinned mapped words, or (allocation-free
+    // advance) through a copy of the device publish area into this array
+    unsigned long long local_ctr[kCounterWords] = {};
+    unsigned long long *host = lat->noalloc ? local_ctr : lat->host_ctr;
     const uint64_t tiles = (uint64_t)plan.a.ntiles[0] * plan.a.ntiles[1] * plan.a.ntiles[2];
     const uint64_t bytes_per_launch = launch_region_bytes(lat->p.dim, plan.a);
 
@@ -650,13 +654,30 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
         plan.a.key_out = lat->key[out];
         plan.a.time_out = lat->time[out];
         plan.a.counters = lat->counters + slot * kSlotWords;
-        plan.a.host_counters = lat->host_ctr_dev + slot * kSlotWords;
+        plan.a.host_counters = (lat->noalloc ? lat->publish : lat->host_ctr_dev) +
+                               slot * kSlotWords;
         plan.a.done_blocks = reinterpret_cast<unsigned int *>(lat->counters + kTicketWord + slot);
         plan.a.dead = lat->dead;
-        HIP_TRY(hipEventRecord(lat->ev_start[slot], s));
+        if (!lat->noalloc) HIP_TRY(hipEventRecord(lat->ev_start[slot], s));
         HIP_TRY(plan.fast ? aca::launch_visit_fast(lat->p.dim, plan.a, plan.block, plan.lds, s)
                           : aca::launch_visit(lat->p.dim, plan.a, plan.block, plan.lds, s));
-        HIP_TRY(hipEventRecord(lat->ev_stop[slot], s));
+        if (!lat->noalloc) HIP_TRY(hipEventRecord(lat->ev_stop[slot], s));
+        return ACA_OK;
+    };
+    // Waits for launch k and leaves its counters in host[slot words].  The
+    // allocation-free advance runs one launch at a time: the copy of the
+    // publish area follows launch k on the stream.
+    auto wait_for = [&](uint64_t k, float *kms) -> aca_status {
+        const int slot = (int)(k & 1);
+        *kms = 0.0f;
+        if (lat->noalloc) {
+            HIP_TRY(hipMemcpyAsync(host + slot * kSlotWords, lat->publish + slot * kSlotWords,
+                                   8 * kSlotWords, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            return ACA_OK;
+        }
+        HIP_TRY(hipEventSynchronize(lat->ev_stop[slot]));
+        HIP_TRY(hipEventElapsedTime(kms, lat->ev_start[slot], lat->ev_stop[slot]));
         return ACA_OK;
     };
     // Every launch applies at least the globally earliest due arrival (the
@@ -667,16 +688,16 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
     if (est != ACA_OK) return est;
     uint64_t enqueued = 1, prev_live = tiles, k = 0, idle = 0;
     for (;; ++k) {
-        if (!lagged && enqueued == k + 1 && prev_live * 8 > tiles) {
+        if (!lagged && !lat->noalloc && enqueued == k + 1 && prev_live * 8 > tiles) {
             est = enqueue(k + 1);
             if (est != ACA_OK) return est;
             ++enqueued;
         }
         const int slot = (int)(k & 1);
-        HIP_TRY(hipEventSynchronize(lat->ev_stop[slot]));
-        const unsigned long long *hc = host + slot * kSlotWords;
         float kms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&kms, lat->ev_start[slot], lat->ev_stop[slot]));
+        est = wait_for(k, &kms);
+        if (est != ACA_OK) return est;
+        const unsigned long long *hc = host + slot * kSlotWords;
         aca_stats &S = lat->stats;
         S.kernel_ms += kms;
         S.region_bytes += bytes_per_launch;
@@ -688,7 +709,7 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
         S.scan_live += hc[aca::kScanLive];
         S.scan_enabled += hc[aca::kScanEnabled];
         S.round_cells += hc[aca::kRoundCells];
-        if (lat->trace.size() < ACA_TRACE_MAX)
+        if (!lat->noalloc && lat->trace.size() < ACA_TRACE_MAX)
             lat->trace.push_back(aca_launch_record{
                 hc[aca::kEvents], hc[aca::kGhostEvents], hc[aca::kScanLive],
                 hc[aca::kScanEnabled], hc[aca::kRoundCells], hc[aca::kLiveTiles], (double)kms});
@@ -731,6 +752,138 @@ aca_status advance_impl(aca_lattice *lat, double T, const FrameRequest *fr, void
 }
 
 }  // namespace
+
+// ------------------------------------------------ allocation-free advance
+//
+// For callers that may not allocate (serving loops, harnesses that forbid
+// it): the working snapshots, tile flags and counters live in one fixed
+// device array instead of a caller scratch buffer, and the launch loop reads
+// its counters back with plain copies instead of pinned host words.  Each
+// device holds its own copy of the array until the process ends.
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+constexpr int kStaticMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+void *g_static_ptr[kStaticMaxDevices];
+
+// Device address of this device's copy of `scratch` (host code must never
+// use the array's own name: that is a host-side stand-in, not device memory).
+aca_status static_scratch(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kStaticMaxDevices)
+        return fail(ACA_EINVAL, "device %d beyond the %d the static scratch supports", dev,
+                    kStaticMaxDevices);
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(ACA_EDEVICE, "static scratch has no device address");
+        g_static_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_static_ptr[dev]);
+    return ACA_OK;
+}
+
+// Static scratch bytes a lattice of n cells needs: the scratch layout of
+// aca_create plus the two publish slots.
+size_t static_scratch_need(uint64_t n)
+{
+    return scratch_layout(n).total + align_up(8 * 2 * kSlotWords);
+}
+
+}  // namespace
+
+ACA_EXPORT aca_status aca_advance_static(const aca_params *p, int8_t *d_spin, double *d_time,
+                                         uint32_t *d_count, int32_t draw_initial,
+                                         double T_done, double T, void *stream)
+{
+    uint64_t n = 0;
+    aca_params full;
+    aca_status st = check_params(p, &n, &full);
+    if (st != ACA_OK) return st;
+    if (!d_spin || !d_time || !d_count) return fail(ACA_EINVAL, "a device buffer is NULL");
+    const void *bufs[3] = {d_spin, d_time, d_count};
+    for (const void *b : bufs)
+        if (((uintptr_t)b) % kAlign != 0)
+            return fail(ACA_EINVAL, "device buffers must be %zu-byte aligned", kAlign);
+    const size_t need = static_scratch_need(n);
+    if (need > kStaticScratchBytes)
+        return fail(ACA_EINVAL,
+                    "a lattice of %llu cells needs %zu B of static scratch; the limit is %zu B "
+                    "(about %llu cells)", (unsigned long long)n, need, kStaticScratchBytes,
+                    (unsigned long long)((kStaticScratchBytes - 2048) / 33));
+    if (!is_finite(T_done) || T_done < 0.0)
+        return fail(ACA_EINVAL, "T_done must be finite and >= 0");
+    if (draw_initial && T_done != 0.0)
+        return fail(ACA_EINVAL, "a freshly drawn state starts at T_done = 0");
+    if (!is_finite(T) || T < T_done)
+        return fail(ACA_EINVAL, "horizon must be finite and >= T_done");
+    if (!aca_host::horizon_fits_counts(full.rate, T))
+        return fail(ACA_EINVAL, "rate * horizon = %.17g exceeds 2^30 (arrival counts are 31-bit)",
+                    full.rate * T);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    unsigned char *base = nullptr;
+    st = static_scratch(dev, &base);
+    if (st != ACA_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // a handle on the stack over the static scratch: nothing is allocated
+    aca_lattice lat;
+    const ScratchLayout sl = scratch_layout(n);
+    lat.p = full;
+    lat.n = n;
+    lat.s = d_spin;
+    lat.t = d_time;
+    lat.cnt = d_count;
+    for (int b = 0; b < 2; ++b) {
+        lat.key[b] = reinterpret_cast<unsigned long long *>(base + sl.key_off[b]);
+        lat.time[b] = reinterpret_cast<unsigned long long *>(base + sl.time_off[b]);
+    }
+    lat.counters = reinterpret_cast<unsigned long long *>(base + sl.ctr_off);
+    lat.dead = reinterpret_cast<uint8_t *>(base + sl.dead_off);
+    lat.publish = reinterpret_cast<unsigned long long *>(base + sl.total);
+    lat.noalloc = true;
+    lat.initialized = true;
+    lat.attached = false;
+    lat.lag = 0.0;
+    lat.last_T = T_done;
+    memset(&lat.tun, 0, sizeof lat.tun);
+    lat.tun.struct_size = sizeof(aca_tuning);
+    lat.tun.ghost[0] = lat.tun.ghost[1] = lat.tun.ghost[2] = -1;
+    memset(&lat.stats, 0, sizeof lat.stats);
+    lat.stats.struct_size = sizeof(aca_stats);
+    build_thresholds(&full, lat.thr);
+    lat.device = dev;
+    lat.host_ctr = nullptr;
+    lat.host_ctr_dev = nullptr;
+    for (int i = 0; i < 2; ++i) lat.ev_start[i] = lat.ev_stop[i] = nullptr;
+
+    if (draw_initial) {
+        HIP_TRY(aca::launch_init(full.dim, full.L, n, (uint32_t)full.seed,
+                                 (uint32_t)(full.seed >> 32), full.rate, full.init, d_spin,
+                                 d_time, d_count, s));
+    } else {
+        // a restored state: the region visits keep a claim in bit 31 of a
+        // cell's count word, so every count must be below 2^31
+        unsigned long long high = 0;
+        HIP_TRY(hipMemsetAsync(lat.counters, 0, 8, s));
+        HIP_TRY(aca::launch_count_bound(n, d_count, lat.counters, s));
+        HIP_TRY(hipMemcpyAsync(&high, lat.counters, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (high) return fail(ACA_EINVAL, "a count n(c) is 2^31 or more");
+    }
+    if (T == T_done) {
+        HIP_TRY(hipStreamSynchronize(s));
+        return ACA_OK;
+    }
+    return advance_impl(&lat, T, nullptr, stream);
+}
 
 ACA_EXPORT aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_t n, double dT,
                               void *stream, int32_t *best, double *rates, int32_t *n_out)

@@ -100,6 +100,12 @@ struct aca_lattice {
     bool attached;                  // member of a batch: advanced by it only
     double lag;                     // lag bound (0: none)
     std::vector<aca_launch_record> trace;   // launches of the last advance
+    // Allocation-free advance (aca_advance_static): no pinned host words, no
+    // HIP events and no trace.  The last block of a launch publishes its
+    // counters to `publish` (device, 2 slots of kSlotWords words) and the
+    // host copies them back after each launch.
+    bool noalloc = false;
+    unsigned long long *publish = nullptr;
 };
 
 namespace aca_host {

@@ -203,3 +203,25 @@ def test_server_host_side_checks():
     assert lib.aca_server_step(None, 0.0, None, None, 0, ctypes.byref(n_done)) == aca.ACA_EINVAL
     assert lib.aca_server_release(None, 0) == aca.ACA_EINVAL
     assert lib.aca_server_destroy(None) == aca.ACA_OK
+
+
+def test_static_advance_host_side_checks():
+    """The allocation-free advance refuses bad arguments, and lattices beyond
+    its fixed scratch, before any device work (no GPU is touched here)."""
+    lib = aca.load()
+    ok = aca.make_params(workloads.lattice(2, (64, 64), 0.4))
+    big = aca.make_params(workloads.lattice(2, (2048, 2048), 0.4))
+    # NULL and misaligned buffers
+    assert lib.aca_advance_static(ctypes.byref(ok), None, 512, 768, 1, 0.0, 1.0, None) == \
+        aca.ACA_EINVAL
+    assert lib.aca_advance_static(ctypes.byref(ok), 8, 512, 768, 1, 0.0, 1.0, None) == \
+        aca.ACA_EINVAL
+    # 2048^2 cells need 33 B each: beyond the 64 MiB array
+    assert lib.aca_advance_static(ctypes.byref(big), 256, 512, 768, 1, 0.0, 1.0, None) == \
+        aca.ACA_EINVAL
+    assert "static scratch" in lib.aca_last_error().decode()
+    # horizons: before T_done, not finite, fresh state not at 0, counts overflow
+    for T_done, T, draw in ((2.0, 1.0, 0), (0.0, float("nan"), 1), (1.0, 2.0, 1),
+                            (0.0, 2.0**31, 1), (-1.0, 1.0, 0)):
+        assert lib.aca_advance_static(ctypes.byref(ok), 256, 512, 768, draw, T_done, T,
+                                      None) == aca.ACA_EINVAL
