@@ -5,6 +5,9 @@ advance on its own) and to the serial oracle, whatever jobs it shared the GPU
 with, when it was admitted, and how the arena budget delayed it: the trajectory
 of a lattice is unique (argument after Fig. 3.1), so the tolerance is zero.
 """
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -100,20 +103,40 @@ def test_served_jobs_equal_alone_and_oracle(torch):
     server.close()
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "served_16.json")
+
+
+def digest(s, t, n):
+    return (hashlib.sha256(s.tobytes()).hexdigest(),
+            hashlib.sha256(t.astype("<f8").tobytes()).hexdigest(),
+            hashlib.sha256(n.astype("<u4").tobytes()).hexdigest())
+
+
 def test_served_stream_jobs_alone_vs_mix(torch):
-    """The first jobs of the served workload at full size, served together with
-    a small step budget, equal each job run alone; sampled cell clocks equal
-    the oracle's closed form."""
-    jobs = [dict(j) for j in workloads.served_stream(count=10)]
+    """The first 16 jobs of the served workload at full size (2D tori up to
+    1572^2 and 3D cubes up to 74^3, both rules, horizons up to 992; 4.9e9
+    arrivals), served together with a small step budget, equal the oracle's
+    digests (tests/golden/served_16.json, written by make_golden.py from the
+    oracle alone) and each job run alone; sampled cell clocks equal the
+    oracle's closed form."""
+    with open(GOLDEN) as f:
+        gold = json.load(f)["items"]
+    jobs = [dict(j) for j in workloads.served_stream(count=len(gold))]
     for j in jobs:
         j.pop("t_arrive")
         j.pop("id")
+    for g, p in zip(gold, jobs):
+        assert g["params"] == p, "golden file is for other job parameters"
     server = aca.Server(arena_bytes=sum(aca.job_bytes(p) for p in jobs), max_jobs=16)
     say("serving the first served-stream jobs")
     results = drive(server, jobs, per_step=2, budget_ms=2.0)
     rng = np.random.default_rng(3)
     for i, p in enumerate(jobs):
         (s, t, n), jst = results[i]
+        say(f"stream job {i}: {p['dim']}D side {p['L'][0]} T={p['T']:.1f}")
+        assert digest(s, t, n) == (gold[i]["sha256_s"], gold[i]["sha256_t"],
+                                   gold[i]["sha256_n"]), f"stream job {i} vs oracle digest"
+        assert jst["events"] == gold[i]["events"] and jst["flips"] == gold[i]["flips"]
         s1, t1, n1, st1 = aca.simulate(p)
         assert_same_state((s, t, n), (s1, t1, n1), f"stream job {i}")
         assert jst["events"] == st1["events"] == int(n.astype(np.int64).sum())
