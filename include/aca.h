@@ -123,7 +123,12 @@ typedef struct aca_stats {
      *    this is exactly the first iteration of Fig. 3.2);
      *  (events + ghost_events) / round_cells: arrivals applied per simulated
      *    cell per worklist round -- each round applies exactly the cells that
-     *    pass the test, so this is N0 / N of Fig. 3.2 inside the regions. */
+     *    pass the test, so this is N0 / N of Fig. 3.2 inside the regions.
+     * The tile visits of the nearest-neighbour rule without output frames
+     * collect these three only while aca_set_counting is on (they cost those
+     * visits a few per cent); the other visits (lattices a tile spans, output
+     * frames, q-th degree neighbourhoods) always collect them.  Batch and
+     * server members never do. */
     uint64_t scan_live;
     uint64_t scan_enabled;
     uint64_t round_cells;   /* simulated cells before the launch's horizon at
@@ -230,6 +235,12 @@ aca_status aca_advance_frames(aca_lattice *lat, double T, double dt, int8_t *d_f
  * previous launch loaded it (0 = no bound).  A schedule knob: results do not
  * change, only the parallelism per launch. */
 aca_status aca_set_lag(aca_lattice *lat, double lag);
+
+/* Whether the lattice's advances collect the efficiency counters of
+ * aca_stats (scan_live, scan_enabled, round_cells) on every path: on != 0
+ * turns them on (default off; results are the same either way).  ACA_ESTATE
+ * for a batch member. */
+aca_status aca_set_counting(aca_lattice *lat, int32_t on);
 
 /* Counters since aca_init (or aca_resume); see aca_stats. */
 aca_status aca_get_stats(const aca_lattice *lat, aca_stats *out);

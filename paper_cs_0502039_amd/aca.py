@@ -31,7 +31,7 @@ EXPORTED = ("aca_abi_version", "aca_last_error", "aca_thresholds", "aca_query",
             "aca_server_load", "aca_server_get_stats", "aca_server_destroy", "aca_tune",
             "aca_batch_tune", "aca_batch_set_order", "aca_server_set_order",
             "aca_advance_frames", "aca_set_lag", "aca_get_thresholds", "aca_get_trace",
-            "aca_advance_static")
+            "aca_advance_static", "aca_set_counting")
 ORDER_WORK, ORDER_ARRIVAL = 0, 1
 TUNE_MAX = 16
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -150,6 +150,7 @@ def load() -> ctypes.CDLL:
         "aca_get_thresholds": [P, P, i32],
         "aca_get_trace": [P, ctypes.POINTER(LaunchRecord), i32, P],
         "aca_advance_static": [pp, P, P, P, i32, f64, f64, P],
+        "aca_set_counting": [P, i32],
         "aca_server_set_order": [P, i32],
         "aca_batch_tune": [P, P, P, i32, i32, pt, i32, f64, P, P, P, P],
         "aca_batch_get_stats": [P, ctypes.POINTER(BatchStats)],
@@ -304,6 +305,11 @@ class Lattice:
         _check(self.lib.aca_advance_frames(self._h, float(T), float(dt),
                                            frames.data_ptr() if nframes else None,
                                            int(k_first), int(nframes), self._s()))
+        return self
+
+    def set_counting(self, on: bool = True) -> "Lattice":
+        """Collect the Section 4 efficiency counters in later advances."""
+        _check(self.lib.aca_set_counting(self._h, 1 if on else 0))
         return self
 
     def set_lag(self, lag: float) -> None:

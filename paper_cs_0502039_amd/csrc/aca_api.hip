@@ -183,10 +183,11 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->max_sweeps = 32; t->block = 512;
     } else {
         // one 20x20x12 region fills most of a CU's LDS: 1024 threads keep
-        // sixteen wavefronts per CU
+        // sixteen wavefronts per CU; later rounds of a 3D visit hold few
+        // cells (a frozen ring one ghost cell away), so visits stop at 12
         t->tile[0] = 20; t->tile[1] = 20; t->tile[2] = 12;
         t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
-        t->max_sweeps = 16; t->block = 1024;
+        t->max_sweeps = 12; t->block = 1024;
     }
 }
 
@@ -293,6 +294,7 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
     a.track_tmin = 0;
     a.frames = nullptr;
     a.n_cells = lat->n;
+    a.count_efficiency = lat->count_efficiency ? 1 : 0;
     memcpy(a.thr, lat->thr, sizeof a.thr);
     plan->block = t.block;
     int dev_lds = 0;
@@ -934,6 +936,14 @@ ACA_EXPORT aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_
     lat->tun = cands[best_k];
     if (best) *best = best_k;
     if (n_out) *n_out = n;
+    return ACA_OK;
+}
+
+ACA_EXPORT aca_status aca_set_counting(aca_lattice *lat, int32_t on)
+{
+    if (!lat) return fail(ACA_EINVAL, "lattice is NULL");
+    if (lat->attached) return fail(ACA_ESTATE, "lattice is a batch member");
+    lat->count_efficiency = on != 0;
     return ACA_OK;
 }
 

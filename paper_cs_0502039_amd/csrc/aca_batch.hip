@@ -305,16 +305,17 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
         const uint32_t in = epoch & 1u;
         const region::Snapshots io{sl.key[in], sl.time[in], sl.key[in ^ 1u], sl.time[in ^ 1u]};
         region::RegionTally r;
-        // unit-rate lattices take the visit without the division by the rate
+        // unit-rate lattices take the visit without the division by the rate;
+        // batch members do not collect the efficiency counters
         if (DIM == 2 || (DIM == 0 && sl.dim == 2))
-            r = a.unit_rate ? region::visit_region<2, false, 1, true>(a, io, tile, lds)
-                            : region::visit_region<2>(a, io, tile, lds);
+            r = a.unit_rate ? region::visit_region<2, false, 1, true, false>(a, io, tile, lds)
+                            : region::visit_region<2, false, 1, false, false>(a, io, tile, lds);
         else if (DIM == 3 || (DIM == 0 && sl.dim == 3))
-            r = a.unit_rate ? region::visit_region<3, false, 1, true>(a, io, tile, lds)
-                            : region::visit_region<3>(a, io, tile, lds);
+            r = a.unit_rate ? region::visit_region<3, false, 1, true, false>(a, io, tile, lds)
+                            : region::visit_region<3, false, 1, false, false>(a, io, tile, lds);
         else
-            r = a.unit_rate ? region::visit_region<1, false, 1, true>(a, io, tile, lds)
-                            : region::visit_region<1>(a, io, tile, lds);
+            r = a.unit_rate ? region::visit_region<1, false, 1, true, false>(a, io, tile, lds)
+                            : region::visit_region<1, false, 1, false, false>(a, io, tile, lds);
         // every wavefront's merge atomics have been performed
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
@@ -328,9 +329,6 @@ batch_visit_kernel(const BatchSlot *slots, BatchState *state, const uint32_t *or
                 atomicAdd(&st.ctr[kGhostEvents], (unsigned long long)r.ghost);
                 atomicAdd(&st.ctr[kChecks], (unsigned long long)r.checks);
                 atomicAdd(&st.ctr[kSweeps], (unsigned long long)r.rounds);
-                atomicAdd(&st.ctr[kScanLive], (unsigned long long)r.scan_live);
-                atomicAdd(&st.ctr[kScanEnabled], (unsigned long long)r.scan_enabled);
-                atomicAdd(&st.ctr[kRoundCells], (unsigned long long)r.round_cells);
                 atomicAdd(&st.epoch_moves, (unsigned long long)(r.events + r.ghost));
                 if (r.any_live) atomicAdd(&st.live, 1u);
                 // a later epoch's visit of this tile may run on another XCD

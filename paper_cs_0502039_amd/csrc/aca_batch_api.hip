@@ -485,9 +485,6 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
             L.sweeps += st.ctr[aca::kSweeps];
             L.ghost_events += st.ctr[aca::kGhostEvents];
             L.cell_checks += st.ctr[aca::kChecks];
-            L.scan_live += st.ctr[aca::kScanLive];
-            L.scan_enabled += st.ctr[aca::kScanEnabled];
-            L.round_cells += st.ctr[aca::kRoundCells];
             L.events += events;
             L.flips += st.sum_flips;
             L.region_bytes += (uint64_t)st.total_epochs * m.region_bytes;

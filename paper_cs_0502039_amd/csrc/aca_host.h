@@ -106,6 +106,7 @@ struct aca_lattice {
     // host copies them back after each launch.
     bool noalloc = false;
     unsigned long long *publish = nullptr;
+    bool count_efficiency = false;  // collect the Section 4 counters (aca_set_counting)
 };
 
 namespace aca_host {

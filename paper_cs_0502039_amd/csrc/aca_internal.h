@@ -73,6 +73,10 @@ struct VisitArgs {
     long long frame_k0;
     long long nframes;
     uint64_t n_cells;
+    // collect the efficiency counters (kScanLive, kScanEnabled, kRoundCells);
+    // the region visits of the nearest-neighbour rule without frames skip
+    // them otherwise
+    int32_t count_efficiency;
 };
 
 // Write `spin` into every frame whose time k dt lies in (t_lo, t_hi]: the

@@ -90,6 +90,15 @@ __device__ __forceinline__ int lanes_below(uint64_t m)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Sum of v over the wavefront, in every lane (cross-lane permutes; every lane
+// of the wavefront must be active).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += (uint32_t)__shfl_xor((int)v, m);
+    return v;
+}
+
 // Pending time of a packed word: the spin is the sign bit and every time is
 // positive, so |word as binary64| is the time (a free source modifier), and
 // binary64 order on these values is the order of their bit patterns.
@@ -264,7 +273,10 @@ struct Snapshots {
 // cells wide.  Q = 1 is the nearest-neighbour visit tuned above; Q > 1 tests
 // and sums over the ball offsets directly.  UNIT: the lattice's rate is 1, so
 // the gap is -ln u itself (the general instantiation divides by the rate).
-template <int DIM, bool FRAMES = false, int Q = 1, bool UNIT = false>
+// COUNT: collect the efficiency counters of Section 4 (scan_live,
+// scan_enabled, round_cells); without it they are zero.  They cost the visit
+// scalar registers, so the visit without them is a kernel of its own.
+template <int DIM, bool FRAMES = false, int Q = 1, bool UNIT = false, bool COUNT = true>
 __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Snapshots io,
                                                     uint32_t tile, unsigned char *lds)
 {
@@ -388,8 +400,9 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // cell still has an arrival before the horizon
     bool due = false;
     uint64_t tmin_own = ~0ull;
-    // owned and simulated cells before the horizon, counted by lane 0 of each
-    // wavefront from ballots (lane 0 takes part in every step its wavefront does)
+    // owned and simulated cells before the horizon, counted per lane (vector
+    // registers: wave-uniform counters would add to the scalar registers the
+    // rounds need) and summed per wavefront after the loop
     uint32_t cnt_own_live = 0, cnt_inner_live = 0;
     for (int j0 = tid; j0 < boxp; j0 += U * nthreads) {
         bool ok[U], inn[U], own[U];
@@ -414,12 +427,12 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 tb[u] = io.time_in[gi[u]];
             }
         }
+        if constexpr (COUNT) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            cnt_own_live += (uint32_t)__popcll(
-                __ballot(ok[u] && own[u] && (uint64_t)tb[u] < a.final_bits));
-            cnt_inner_live += (uint32_t)__popcll(
-                __ballot(ok[u] && inn[u] && (uint64_t)tb[u] < a.horizon_bits));
+            for (int u = 0; u < U; ++u) {
+                cnt_own_live += (ok[u] && own[u] && (uint64_t)tb[u] < a.final_bits) ? 1u : 0u;
+                cnt_inner_live += (ok[u] && inn[u] && (uint64_t)tb[u] < a.horizon_bits) ? 1u : 0u;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -437,8 +450,14 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         }
     }
     if (a.track_tmin && tmin_own != ~0ull) atomicMin(tmin_slot, tmin_own);
-    if (lane == 0 && cnt_own_live) atomicAdd(&ctr[10], (int)cnt_own_live);
-    if (lane == 0 && cnt_inner_live) atomicAdd(&ctr[12], (int)cnt_inner_live);
+    if constexpr (COUNT) {
+        // a region box has fewer than 2^16 cells, so both sums fit 16 bits
+        const uint32_t both = wave_sum(cnt_own_live | (cnt_inner_live << 16));
+        if (lane == 0 && both) {
+            atomicAdd(&ctr[10], (int)(both & 0xFFFFu));
+            atomicAdd(&ctr[12], (int)(both >> 16));
+        }
+    }
     const int own_due = __syncthreads_or(due ? 1 : 0);
     if (a.track_tmin && tid == 0 && *tmin_slot != ~0ull)
         atomicMin(&a.counters[kTminBits], (unsigned long long)*tmin_slot);
@@ -513,7 +532,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // per thread per step (their reads issued together, one list atomic per
     // wavefront for all of them; nearest neighbours only)
     constexpr int US = Q == 1 ? 4 : 1;   // a wider reach has no registers to spare
-    uint32_t cnt_scan_own = 0;   // owned cells listed (lane 0 of each wavefront)
+    uint32_t cnt_scan_own = 0;   // owned cells this lane listed
     for (int base = tid - lane; base < boxp; base += US * nthreads) {
         bool en[US], owned[US];
         int cell[US];
@@ -559,7 +578,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         for (int u = 0; u < US; ++u) {
             m[u] = __ballot(en[u]);
             total += (int)__popcll(m[u]);
-            cnt_scan_own += (uint32_t)__popcll(__ballot(en[u] && owned[u]));
+            if constexpr (COUNT) cnt_scan_own += (en[u] && owned[u]) ? 1u : 0u;
         }
         if (total) {
             int b0 = 0;
@@ -572,7 +591,10 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             }
         }
     }
-    if (lane == 0 && cnt_scan_own) atomicAdd(&ctr[11], (int)cnt_scan_own);
+    if constexpr (COUNT) {
+        cnt_scan_own = wave_sum(cnt_scan_own);
+        if (lane == 0 && cnt_scan_own) atomicAdd(&ctr[11], (int)cnt_scan_own);
+    }
     __syncthreads();
 
     // ---- worklist rounds

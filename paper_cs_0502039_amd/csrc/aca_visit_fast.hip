@@ -12,24 +12,19 @@
 namespace aca {
 namespace {
 
-template <int DIM, bool FRAMES, int Q>
+// UNIT: the lattice's rate is 1 (no division in the gap); COUNT: collect the
+// efficiency counters.  The nearest-neighbour visit without frames comes in
+// all four combinations, each a kernel of its own so that none carries
+// another's registers; the other visits always count and divide by the rate.
+template <int DIM, bool FRAMES, int Q, bool UNIT = false, bool COUNT = true>
 __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const unsigned int ntiles_total = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                                       (unsigned)a.ntiles[2];
     const region::Snapshots io{a.key_in, a.time_in, a.key_out, a.time_out};
-    region::RegionTally r;
-    if constexpr (Q == 1 && !FRAMES) {
-        // the nearest-neighbour visit without frames has a unit-rate variant
-        // (no division in the gap); the branch is uniform over the launch
-        if (a.unit_rate)
-            r = region::visit_region<DIM, false, 1, true>(a, io, blockIdx.x, lds);
-        else
-            r = region::visit_region<DIM, false, 1, false>(a, io, blockIdx.x, lds);
-    } else {
-        r = region::visit_region<DIM, FRAMES, Q>(a, io, blockIdx.x, lds);
-    }
+    const region::RegionTally r =
+        region::visit_region<DIM, FRAMES, Q, UNIT, COUNT>(a, io, blockIdx.x, lds);
     if (threadIdx.x == 0) {
         if (!r.skipped) {
             unsigned long long *gc = a.counters;
@@ -38,9 +33,11 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
             atomicAdd(&gc[kGhostEvents], (unsigned long long)r.ghost);
             atomicAdd(&gc[kChecks], (unsigned long long)r.checks);
             atomicAdd(&gc[kSweeps], (unsigned long long)r.rounds);
-            atomicAdd(&gc[kScanLive], (unsigned long long)r.scan_live);
-            atomicAdd(&gc[kScanEnabled], (unsigned long long)r.scan_enabled);
-            atomicAdd(&gc[kRoundCells], (unsigned long long)r.round_cells);
+            if (COUNT) {
+                atomicAdd(&gc[kScanLive], (unsigned long long)r.scan_live);
+                atomicAdd(&gc[kScanEnabled], (unsigned long long)r.scan_enabled);
+                atomicAdd(&gc[kRoundCells], (unsigned long long)r.round_cells);
+            }
             if (r.any_live) atomicAdd(&gc[kLiveTiles], 1ull);
             // owned cells that were all at or past the horizon when loaded can
             // never change again: both snapshots now hold them
@@ -51,11 +48,29 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
 }
 
 // Every (dimension, frames, reach) instantiation: reach 1..4 in 1D, 1..3 in
-// 2D, 1..2 in 3D.
+// 2D, 1..2 in 3D; plus the unit-rate nearest-neighbour visits without frames.
 template <int DIM, bool FRAMES, int Q>
 const void *fast_fn()
 {
     return (const void *)visit_fast_kernel<DIM, FRAMES, Q>;
+}
+
+template <bool UNIT, bool COUNT>
+const void *near_fn(int dim)
+{
+    switch (dim) {
+    case 1: return (const void *)visit_fast_kernel<1, false, 1, UNIT, COUNT>;
+    case 2: return (const void *)visit_fast_kernel<2, false, 1, UNIT, COUNT>;
+    case 3: return (const void *)visit_fast_kernel<3, false, 1, UNIT, COUNT>;
+    default: return nullptr;
+    }
+}
+
+// The nearest-neighbour visit without frames, by rate and counting.
+const void *near_fast_kernel(int dim, bool unit, bool count)
+{
+    if (unit) return count ? near_fn<true, true>(dim) : near_fn<true, false>(dim);
+    return count ? near_fn<false, true>(dim) : near_fn<false, false>(dim);
 }
 
 template <bool FRAMES>
@@ -109,7 +124,10 @@ hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
 {
     const unsigned tiles = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                            (unsigned)a.ntiles[2];
-    const void *fn = fast_kernel(dim, a.range > 1 ? a.range : 1, a.frames != nullptr);
+    const int q = a.range > 1 ? a.range : 1;
+    const void *fn = (q == 1 && !a.frames)
+                         ? near_fast_kernel(dim, a.unit_rate != 0, a.count_efficiency != 0)
+                         : fast_kernel(dim, q, a.frames != nullptr);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {const_cast<VisitArgs *>(&a)};
     return hipLaunchKernel(fn, dim3(tiles), dim3(block), args, lds, stream);
@@ -126,6 +144,13 @@ hipError_t set_visit_fast_lds_limit(size_t bytes)
                     hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                 if (e != hipSuccess) return e;
             }
+    for (int dim = 1; dim <= 3; ++dim)
+        for (int v = 0; v < 4; ++v) {
+            const hipError_t e = hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)bytes);
+            if (e != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 

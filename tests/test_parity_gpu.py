@@ -494,7 +494,7 @@ def test_first_launch_scan_is_round_one_of_fig_3_2(torch, params):
     live = int((t < params["T"]).sum())
     _, rounds, _, rec = oracle.run_rounds(params, params["T"], s.copy(), t.copy(), n.copy(),
                                           times_only=True, max_record=4)
-    lat = aca.Lattice(params).init().advance(params["T"])
+    lat = aca.Lattice(params).set_counting().init().advance(params["T"])
     tr = lat.trace()
     st = lat.stats()
     lat.close()
