@@ -11,7 +11,8 @@ Prints one JSON line.  Besides the contract fields it carries
                 per launch over the launch time measured with HIP events on the
                 launching stream (inside the library), against MI355X peaks;
   cpu_baseline  the serial oracle timed on a bounded sample of the same workload
-                on one host core;
+                on one host core, the host's CPU model and core count, and an
+                all-core aggregate (one batch lattice per worker process);
   batched       the 512-lattice workload (sides log-uniform in [32, 1024],
                 uneven temperatures and horizons): one batch advance against the
                 plain path of one init + advance per lattice on one stream, in
@@ -19,7 +20,10 @@ Prints one JSON line.  Besides the contract fields it carries
   served        the job stream (80% 2D up to 2048^2, 20% 3D up to 128^3, both
                 rules, horizons up to 1000) through the job server: first all
                 jobs at once (capacity in jobs/s), then Poisson arrivals at 0.7
-                of that capacity, with p50/p99 of result-on-host minus arrival.
+                of that capacity, with p50/p99 of result-on-host minus arrival;
+                the same jobs through the plain path (one init + advance per
+                job, in arrival order) for the served-vs-plain speedup, and the
+                2D and 3D jobs served apart.
 """
 from __future__ import annotations
 
@@ -102,6 +106,21 @@ def copy_calibration(nbytes: int = 1 << 31) -> None:
     log(f"copy calibration: {nbytes} bytes read and {nbytes} bytes written")
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "usable_cores": len(os.sched_getaffinity(0)),
+            "os_cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(params: dict, T_sample: float) -> dict:
     import oracle
     log(f"cpu_baseline: oracle on {params['L']} to T={T_sample}")
@@ -112,10 +131,65 @@ def cpu_baseline(params: dict, T_sample: float) -> dict:
     t2 = time.time()
     rate = ev / (t2 - t1)
     return {"value": rate, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
             "sample": (f"{params['L'][0]}^{params['dim']} lattice seed {params['seed']}, "
                        f"binary-heap oracle from the initial state to T={T_sample} "
                        f"({ev} arrivals in {t2 - t1:.1f} s; init {t1 - t0:.1f} s not "
-                       f"counted)")}
+                       f"counted), one thread")}
+
+
+# arrivals per worker in the all-core sample (about 10 s of one core each)
+AGGREGATE_ARRIVALS = 2.0e7
+
+
+def _oracle_item(params):
+    import oracle
+    t0 = time.time()
+    s, t, n = oracle.init(params)
+    ev, _ = oracle.run(params, params["T"], s, t, n)
+    return ev, time.time() - t0
+
+
+def cpu_aggregate_main(workers: int) -> None:
+    """All-core oracle on the 512-lattice workload (runs in its own interpreter,
+    which never touches the GPU): the first `workers` lattices, one per worker
+    process, each to min(T, the horizon of about AGGREGATE_ARRIVALS arrivals)."""
+    from multiprocessing import Pool
+    from paper_cs_0502039_amd import workloads
+    import oracle
+    oracle.lib()
+    items = []
+    for p in workloads.batch_512()[:workers]:
+        n = p["L"][0] * p["L"][1]
+        items.append(dict(p, T=min(p["T"], AGGREGATE_ARRIVALS / n)))
+    t0 = time.time()
+    with Pool(workers) as pool:
+        res = pool.map(_oracle_item, items)
+    wall = time.time() - t0
+    events = sum(r[0] for r in res)
+    print(json.dumps({"events": events, "wall_s": wall, "workers": workers,
+                      "per_worker_rate": [r[0] / r[1] for r in res],
+                      "sides": [p["L"][0] for p in items],
+                      "horizons": [p["T"] for p in items]}), flush=True)
+
+
+def cpu_aggregate(max_workers: int = 16) -> dict:
+    """The all-core leg of the CPU baseline, in a child interpreter."""
+    import subprocess
+    workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    log(f"cpu_baseline: all-core oracle aggregate, {workers} workers")
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-aggregate-only",
+                          str(workers)], capture_output=True, text=True, timeout=600)
+    if res.returncode != 0:
+        return {"error": res.stderr[-500:]}
+    doc = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": doc["events"] / doc["wall_s"], "unit": "spin-updates/s",
+            "cores": workers, "kind": "oracle",
+            "per_core": doc["events"] / doc["wall_s"] / workers,
+            "sample": (f"the first {workers} lattices of the 512-lattice workload (sides "
+                       f"{min(doc['sides'])}-{max(doc['sides'])}), one per worker process, "
+                       f"each to min(T, {AGGREGATE_ARRIVALS:.0e} / N): {doc['events']} "
+                       f"arrivals in {doc['wall_s']:.1f} s wall")}
 
 
 def bench_batched(steps: int, warmup: int, autotune: bool = True) -> dict:
@@ -245,9 +319,23 @@ def bench_served(arena_gib: float, max_jobs: int, budget_ms: float, count: int) 
     arrivals = [t / rho for t in unit_arrivals]
     lat, wall, st = serve(jobs, arena, max_jobs, budget_ms, arrivals)
     lat_ms = np.array(lat) * 1e3
+    # the same jobs served per dimension alone: where the device time goes
+    by_dim = {}
+    for dim in (2, 3):
+        sub = [j for j in jobs if j["dim"] == dim]
+        _, wall_d, st_d = serve(sub, arena, max_jobs, budget_ms)
+        by_dim[f"{dim}d"] = {"jobs": len(sub), "served_s": wall_d,
+                             "spin_updates": st_d["events"],
+                             "spin_updates_per_s": st_d["events"] / wall_d}
+    plain = bench_served_plain(jobs)
+    log(f"served: plain path {plain['jobs_per_s']:.1f} jobs/s; served capacity "
+        f"{capacity:.1f} jobs/s ({capacity / plain['jobs_per_s']:.2f}x)")
     return {"workload": "served_stream", "jobs": count, "arena_gib": arena_gib,
             "max_jobs": max_jobs, "step_budget_ms": budget_ms,
             "capacity_jobs_per_s": capacity,
+            "plain_jobs_per_s": plain["jobs_per_s"],
+            "speedup_vs_plain": capacity / plain["jobs_per_s"],
+            "plain": plain, "by_dim": by_dim,
             "capacity_spin_updates_per_s": st_c["events"] / wall_c,
             "rho_jobs_per_s": rho, "jobs_per_s": count / wall,
             "spin_updates_per_s": st["events"] / wall,
@@ -256,6 +344,36 @@ def bench_served(arena_gib: float, max_jobs: int, budget_ms: float, count: int) 
             "max_ms": float(lat_ms.max()), "mean_ms": float(lat_ms.mean()),
             "events": st["events"], "steps": st["steps"],
             "arena_peak_gib": st["arena_peak"] / (1 << 30), "queued_peak": st["queued_peak"]}
+
+
+def bench_served_plain(jobs) -> dict:
+    """The plain path on the served mix: for each job in arrival order, its own
+    state buffers, one aca_init + aca_advance on one stream, and the result read
+    to the host, one job after another."""
+    import torch
+    from paper_cs_0502039_amd import aca
+    warm = aca.Lattice(dict(jobs[0], L=[32] * jobs[0]["dim"]))
+    warm.init().advance(1.0)
+    warm.close()
+    torch.cuda.synchronize()
+    per_dim = {2: [0, 0.0, 0], 3: [0, 0.0, 0]}
+    t0 = time.perf_counter()
+    for p in jobs:
+        t1 = time.perf_counter()
+        lat = aca.Lattice(p)
+        lat.init().advance(p["T"])
+        lat.read()
+        ev = lat.stats()["events"]
+        lat.close()
+        d = per_dim[p["dim"]]
+        d[0] += 1
+        d[1] += time.perf_counter() - t1
+        d[2] += ev
+    wall = time.perf_counter() - t0
+    return {"jobs": len(jobs), "wall_s": wall, "jobs_per_s": len(jobs) / wall,
+            "spin_updates_per_s": sum(d[2] for d in per_dim.values()) / wall,
+            "by_dim": {f"{k}d": {"jobs": v[0], "s": v[1], "spin_updates": v[2]}
+                       for k, v in per_dim.items()}}
 
 
 def bench_lag(lags, T: float = 50.0, frame_dt: float = 5.0) -> dict:
@@ -370,11 +488,22 @@ def main() -> int:
     # (admission, pack/unpack, the counter read-back) over more epochs; the
     # step length also bounds how long a finished job waits to be reported
     ap.add_argument("--serve-budget-ms", type=float, default=16.0)
+    ap.add_argument("--no-cpu-aggregate", action="store_true")
+    ap.add_argument("--cpu-aggregate-only", type=int, default=0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_aggregate_only:
+        cpu_aggregate_main(args.cpu_aggregate_only)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU only; the workload is a single lattice on "
               "one device, and runs over several GPUs are not supported.", file=sys.stderr)
         return 2
+
+    # the all-core oracle runs in a child interpreter, started before this
+    # process touches the GPU
+    aggregate = None
+    if args.only is None and not (args.no_cpu_baseline or args.no_cpu_aggregate):
+        aggregate = cpu_aggregate()
 
     import torch
     from paper_cs_0502039_amd import aca, workloads
@@ -441,6 +570,13 @@ def main() -> int:
 
     st = stats[-1]
     events = st["events"]
+    # Section 4's efficiency counters cost the visit a few per cent, so the
+    # timed steps run without them; one more advance, untimed, collects them
+    lat.set_counting(True)
+    lat.init().advance(T)
+    st_eff = lat.stats()
+    trace = lat.trace()
+    lat.set_counting(False)
     ms_per_step = 1e3 * elapsed / args.steps
     value = events / (elapsed / args.steps)
 
@@ -499,6 +635,22 @@ def main() -> int:
         "sweeps_per_visit": st["sweeps"] / st["visits"],
         "enabled_per_check": (events + st["ghost_events"]) / max(1, st["cell_checks"]),
         "ghost_events_per_event": st["ghost_events"] / max(1, events),
+        # Section 4's efficiency N0 / N: the fraction of cells that pass the
+        # enabling test at an iteration.  first_scan: the first launch's scan
+        # of the initial state (the first synchronous iteration, expected
+        # 1/(z+1)); scan: every launch's initial scan over the owned cells
+        # before the horizon; per_round: arrivals applied per simulated cell
+        # per worklist round inside the regions.  The paper's long-run 2D
+        # value of the synchronous iteration is 0.121.
+        "efficiency": {
+            "first_scan": trace[0]["scan_enabled"] / max(1, trace[0]["scan_live"]),
+            "scan": st_eff["scan_enabled"] / max(1, st_eff["scan_live"]),
+            "per_round": (st_eff["events"] + st_eff["ghost_events"])
+            / max(1, st_eff["round_cells"]),
+            "paper_2d_long_run": 0.121},
+        # what a captured graph of the launch loop could save at most: the
+        # advance's wall time less its kernels' time
+        "launch_gap_ms_per_step": st["device_ms"] - st["kernel_ms"],
     }
     lat.close()
     del lat
@@ -509,6 +661,8 @@ def main() -> int:
                                      args.serve_budget_ms, args.serve_jobs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(params, args.cpu_sample_T)
+        if aggregate is not None:
+            out["cpu_baseline"]["all_cores_batch_512"] = aggregate
     print(json.dumps(out), flush=True)
     return 0
 
