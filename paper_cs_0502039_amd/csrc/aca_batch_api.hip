@@ -29,6 +29,8 @@ constexpr uint32_t kMaxPackBlocks = 1024;  // per member
 // A workgroup that finds no open item for this long gives up; the step then
 // reports ACA_ENOPROGRESS instead of waiting for ever.
 constexpr double kWaitLimitSeconds = 20.0;
+// Static LDS of the persistent visit kernel (its item words), with room to spare.
+constexpr size_t kBatchStaticLds = 256;
 // aca_batch_advance returns to the host at least this often.
 constexpr double kAdvanceStepMs = 1000.0;
 // Tiles per member stay far below the closed-claim mark of the claim words.
@@ -402,14 +404,24 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
         std::stable_sort(prio.begin(), prio.end(), [&](int x, int y) {
             return b->member[x].work > b->member[y].work;
         });
-    int dim = b->member[mem[0]].lat->p.dim;
-    size_t lds = 0;
+    // Members whose regions leave room for two workgroups per compute unit
+    // (class 0) and the others (class 1) run in launches of their own, one
+    // after the other: a launch gives every workgroup the largest region of
+    // its members, so one large 3D region would otherwise halve the
+    // workgroups of every 2D member.
+    int lds_per_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_per_cu,
+                                  hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, b->device));
+    auto cls = [&](const Member &m) { return 2 * (m.lds + kBatchStaticLds) <= (size_t)lds_per_cu ? 0 : 1; };
+    int dim_c[2] = {-1, -1};
+    size_t lds_c[2] = {0, 0};
+    uint64_t work_c[2] = {0, 0};
+    uint32_t n_c[2] = {0, 0};
     uint32_t njoin = 0, jblocks = 0, mblocks = 0;
     int max_slot = 0;
     for (size_t i = 0; i < mem.size(); ++i) {
         const int sl = mem[i];
         const Member &m = b->member[sl];
-        h_order[i] = (uint32_t)prio[i];
         h_mem[i] = (uint32_t)sl;
         h_mem_start[i] = mblocks;
         mblocks += pack_blocks(m.lat->n);
@@ -419,21 +431,31 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
             jblocks += pack_blocks(m.lat->n);
             ++njoin;
         }
-        if (m.lat->p.dim != dim) dim = 0;
-        lds = std::max(lds, m.lds);
+        const int c = cls(m);
+        dim_c[c] = dim_c[c] < 0 ? m.lat->p.dim : (dim_c[c] == m.lat->p.dim ? dim_c[c] : 0);
+        lds_c[c] = std::max(lds_c[c], m.lds);
+        work_c[c] += m.work;
+        ++n_c[c];
         max_slot = std::max(max_slot, sl);
     }
+    // the priority order, class 0's members first, then class 1's
+    uint32_t fill[2] = {0, n_c[0]};
+    for (int sl : prio) h_order[fill[cls(b->member[sl])]++] = (uint32_t)sl;
     const uint32_t nmem = (uint32_t)mem.size();
     h_mem_start[nmem] = mblocks;
     h_join_start[njoin] = jblocks;
 
-    if (lds > b->lds_limit_set) {
-        HIP_TRY(aca::set_batch_lds_limit(lds));
-        b->lds_limit_set = lds;
+    const size_t lds_max = std::max(lds_c[0], lds_c[1]);
+    if (lds_max > b->lds_limit_set) {
+        HIP_TRY(aca::set_batch_lds_limit(lds_max));
+        b->lds_limit_set = lds_max;
     }
-    int blocks = 0;
-    HIP_TRY(aca::batch_max_blocks(dim, lds, &blocks));
-    if (blocks < 1) return fail(ACA_EINVAL, "the batch kernel does not fit a compute unit");
+    int blocks_c[2] = {0, 0};
+    for (int c = 0; c < 2; ++c) {
+        if (!n_c[c]) continue;
+        HIP_TRY(aca::batch_max_blocks(dim_c[c], lds_c[c], &blocks_c[c]));
+        if (blocks_c[c] < 1) return fail(ACA_EINVAL, "the batch kernel does not fit a compute unit");
+    }
 
     if (njoin) {
         HIP_TRY(hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(aca::BatchSlot) * (max_slot + 1),
@@ -448,16 +470,31 @@ ACA_EXPORT aca_status aca_batch_step(aca_batch *b, double budget_ms, int32_t max
                            hipMemcpyHostToDevice, s));
     HIP_TRY(aca::launch_batch_pack(b->d_slots, b->d_state, b->d_joining, b->d_joining_start,
                                    njoin, jblocks, s));
-    const unsigned long long budget_ticks =
-        budget_ms > 0.0 ? (unsigned long long)std::max(1.0, budget_ms * 1e-3 * b->wall_hz) : 0ull;
     const unsigned long long epochs_cap =
         max_epochs > 0 ? (unsigned long long)max_epochs : ~0ull;
-    HIP_TRY(aca::launch_batch_open(b->d_state, b->d_members, nmem, b->d_g, budget_ticks,
-                                   epochs_cap, s));
+    // With both classes present the step's budget is shared in proportion to
+    // their remaining arrivals (at least a quarter each); a launch whose
+    // members all finish ends early anyway.
+    const uint64_t work_all = work_c[0] + work_c[1];
     HIP_TRY(hipEventRecord(b->ev0, s));
-    HIP_TRY(aca::launch_batch_visit(dim, b->d_slots, b->d_state, b->d_order, nmem, b->d_g,
-                                    (unsigned long long)(kWaitLimitSeconds * b->wall_hz),
-                                    blocks, lds, s));
+    uint32_t first = 0;
+    for (int c = 0; c < 2; ++c) {
+        if (!n_c[c]) continue;
+        double share = 1.0;
+        if (n_c[0] && n_c[1] && work_all > 0)
+            share = std::min(1.0, std::max(0.25, (double)work_c[c] / (double)work_all));
+        const unsigned long long budget_ticks =
+            budget_ms > 0.0
+                ? (unsigned long long)std::max(1.0, share * budget_ms * 1e-3 * b->wall_hz)
+                : 0ull;
+        HIP_TRY(aca::launch_batch_open(b->d_state, b->d_order + first, n_c[c], b->d_g,
+                                       budget_ticks, epochs_cap, s));
+        HIP_TRY(aca::launch_batch_visit(dim_c[c], b->d_slots, b->d_state, b->d_order + first,
+                                        n_c[c], b->d_g,
+                                        (unsigned long long)(kWaitLimitSeconds * b->wall_hz),
+                                        blocks_c[c], lds_c[c], s));
+        first += n_c[c];
+    }
     HIP_TRY(hipEventRecord(b->ev1, s));
     HIP_TRY(aca::launch_batch_unpack(b->d_slots, b->d_state, b->d_members, b->d_members_start,
                                      nmem, mblocks, s));
