@@ -216,16 +216,21 @@ struct FastPlan {
         list_cap, total;
 };
 
-// Pitched box: pitch[d] = the largest region box side along d in this launch.
-__host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim)
+// Pitch of the region box along each direction: the box side of the plan's
+// tiles (the largest region of the launch), 1 beyond the lattice's dimension.
+__host__ __device__ inline void box_pitch(const VisitArgs &a, int dim, int *pitch)
 {
     // the frozen ring is as wide as the neighbourhood's reach
     const int ring = a.range > 1 ? a.range : 1;
-    int pitch[3] = {1, 1, 1}, inner = 1;
-    for (int d = 0; d < dim; ++d) {
-        pitch[d] = a.tile[d] + 2 * a.ghost[d] + 2 * ring;
-        inner *= a.tile[d] + 2 * a.ghost[d];
-    }
+    for (int d = 0; d < 3; ++d) pitch[d] = d < dim ? a.tile[d] + 2 * a.ghost[d] + 2 * ring : 1;
+}
+
+// LDS layout of a region box with the given pitches.
+__host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim, const int *pitch)
+{
+    const int ring = a.range > 1 ? a.range : 1;
+    int inner = 1;
+    for (int d = 0; d < dim; ++d) inner *= a.tile[d] + 2 * a.ghost[d];
     const size_t boxp = (size_t)pitch[0] * pitch[1] * pitch[2];
     // neighbours the rule reads: 2 dim, or the ball of radius `ring`
     int z = 2 * dim;
@@ -259,6 +264,13 @@ __host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim)
     return p;
 }
 
+__host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim)
+{
+    int pitch[3];
+    box_pitch(a, dim, pitch);
+    return fast_plan(a, dim, pitch);
+}
+
 // The snapshots a visit reads and merges into.
 struct Snapshots {
     const unsigned long long *key_in;
@@ -276,7 +288,12 @@ struct Snapshots {
 // COUNT: collect the efficiency counters of Section 4 (scan_live,
 // scan_enabled, round_cells); without it they are zero.  They cost the visit
 // scalar registers, so the visit without them is a kernel of its own.
-template <int DIM, bool FRAMES = false, int Q = 1, bool UNIT = false, bool COUNT = true>
+// CP0, CP1, CP2: the box pitches as compile-time constants (0: taken from the
+// plan at run time).  The caller must only pass constants equal to the plan's
+// pitches (box_pitch); with them the LDS layout and every stencil offset fold
+// into constants, and the stencil reads of an arrival share one base address.
+template <int DIM, bool FRAMES = false, int Q = 1, bool UNIT = false, bool COUNT = true,
+          int CP0 = 0, int CP1 = 0, int CP2 = 0>
 __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Snapshots io,
                                                     uint32_t tile, unsigned char *lds)
 {
@@ -316,13 +333,19 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             side[d] = 1; rin[d] = 1; org[d] = 0; olo[d] = 0; ohi[d] = 1; pitch[d] = 1;
         }
     }
+    constexpr bool kConstPitch = CP0 > 0;
+    if constexpr (kConstPitch) {
+        pitch[0] = CP0;
+        pitch[1] = CP1 > 0 ? CP1 : 1;
+        pitch[2] = CP2 > 0 ? CP2 : 1;
+    }
     const int P1 = pitch[0], P12 = pitch[0] * pitch[1];
     const int rb[3] = {DIM > 0 ? rin[0] + 2 * Q : 1, DIM > 1 ? rin[1] + 2 * Q : 1,
                        DIM > 2 ? rin[2] + 2 * Q : 1};
     const uint32_t magic1 = 0xFFFFFFFFu / (uint32_t)P1 + 1u;            // P1 >= 3
     const uint32_t magic2 = pitch[1] > 1 ? 0xFFFFFFFFu / (uint32_t)pitch[1] + 1u : 0u;
 
-    const FastPlan plan = fast_plan(a, DIM);
+    const FastPlan plan = fast_plan(a, DIM, pitch);
     uint64_t *thr = reinterpret_cast<uint64_t *>(lds + plan.thr_off);
     int *ctr = reinterpret_cast<int *>(lds + plan.ctr_off);
     uint32_t *tx = reinterpret_cast<uint32_t *>(lds + plan.tab_off);
@@ -690,8 +713,18 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 }
                 // the cell and its neighbour slots: stable until it applies
                 // its arrival (no neighbour can be enabled meanwhile)
+                if constexpr (kConstPitch) {
+                    // one base register below the stencil, non-negative
+                    // constant offsets (LDS immediates are unsigned)
+                    constexpr int omin = -2 * (DIM > 2 ? CP0 * CP1 : (DIM > 1 ? CP0 : 1));
+                    int wb = bi + omin;
+                    __asm__("" : "+v"(wb));
 #pragma unroll
-                for (int k = 0; k <= Z; ++k) W[k] = ldw(&ts[bi + off(k)]);
+                    for (int k = 0; k <= Z; ++k) W[k] = ldw(&ts[wb + (off(k) - omin)]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k <= Z; ++k) W[k] = ldw(&ts[bi + off(k)]);
+                }
                 own_tmin = horizon_t;
 #pragma unroll
                 for (int k = 1; k <= Z; ++k) own_tmin = __builtin_fmin(own_tmin, time_of(W[k]));
@@ -724,14 +757,23 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             // both new words, so a neighbour they both unblocked is found.
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
             if (active) {
+                int wb = bi;
+                constexpr int omin = kConstPitch ? -2 * (DIM > 2 ? CP0 * CP1 : (DIM > 1 ? CP0 : 1)) : 0;
+                if constexpr (kConstPitch) {
+                    wb = bi + omin;
+                    __asm__("" : "+v"(wb));
+                }
 #pragma unroll
                 for (int k = Z + 1; k < K; ++k) {
-                    int at = bi + off(k);
-                    // two steps along z may leave the box (and its guard);
-                    // such words are never used, so any in-range address will do
-                    if (DIM > 2 && (S.d[k][2] == 2 || S.d[k][2] == -2))
-                        at = min(max(at, 0), boxp - 1);
-                    W[k] = ldw(&ts[at]);
+                    if (DIM > 2 && (S.d[k][2] == 2 || S.d[k][2] == -2)) {
+                        // two steps along z may leave the box (and its guard);
+                        // such words are never used, so any in-range address will do
+                        W[k] = ldw(&ts[min(max(bi + off(k), 0), boxp - 1)]);
+                    } else if constexpr (kConstPitch) {
+                        W[k] = ldw(&ts[wb + (off(k) - omin)]);
+                    } else {
+                        W[k] = ldw(&ts[bi + off(k)]);
+                    }
                 }
             }
             // re-test the applied cell (s = 0) and its neighbours (s = 1..Z):
@@ -783,8 +825,17 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 take[s] = want[s] ? kClaim : 0u;
             }
             if (active) {
+                if constexpr (kConstPitch) {
+                    constexpr int omin1 = -(DIM > 2 ? CP0 * CP1 : (DIM > 1 ? CP0 : 1));
+                    int nb0 = bi + omin1;
+                    __asm__("" : "+v"(nb0));
 #pragma unroll
-                for (int s = 1; s <= Z; ++s) take[s] &= ~atomicOr(&nl[cb[s]], take[s]);
+                    for (int s = 1; s <= Z; ++s)
+                        take[s] &= ~atomicOr(&nl[nb0 + (off(s) - omin1)], take[s]);
+                } else {
+#pragma unroll
+                    for (int s = 1; s <= Z; ++s) take[s] &= ~atomicOr(&nl[cb[s]], take[s]);
+                }
             }
             // one LDS atomic per wavefront for all its new list entries
             uint64_t mk[Z + 1];

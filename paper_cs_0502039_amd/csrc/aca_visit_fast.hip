@@ -16,7 +16,10 @@ namespace {
 // efficiency counters.  The nearest-neighbour visit without frames comes in
 // all four combinations, each a kernel of its own so that none carries
 // another's registers; the other visits always count and divide by the rate.
-template <int DIM, bool FRAMES, int Q, bool UNIT = false, bool COUNT = true>
+// CP0..CP2: compile-time box pitches (0: from the plan), for the default
+// tiles of the large lattices.
+template <int DIM, bool FRAMES, int Q, bool UNIT = false, bool COUNT = true, int CP0 = 0,
+          int CP1 = 0, int CP2 = 0>
 __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -24,7 +27,7 @@ __global__ void __launch_bounds__(1024) visit_fast_kernel(VisitArgs a)
                                       (unsigned)a.ntiles[2];
     const region::Snapshots io{a.key_in, a.time_in, a.key_out, a.time_out};
     const region::RegionTally r =
-        region::visit_region<DIM, FRAMES, Q, UNIT, COUNT>(a, io, blockIdx.x, lds);
+        region::visit_region<DIM, FRAMES, Q, UNIT, COUNT, CP0, CP1, CP2>(a, io, blockIdx.x, lds);
     if (threadIdx.x == 0) {
         if (!r.skipped) {
             unsigned long long *gc = a.counters;
@@ -66,9 +69,24 @@ const void *near_fn(int dim)
     }
 }
 
-// The nearest-neighbour visit without frames, by rate and counting.
-const void *near_fast_kernel(int dim, bool unit, bool count)
+// Box pitches compiled as constants: the default region of a 2D lattice (a
+// 64 x 56 tile with 4 ghost cells a side) and of a 3D one (20 x 20 x 12 with 1).
+constexpr int kPitch2[3] = {64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 1};
+constexpr int kPitch3[3] = {20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 12 + 2 * 1 + 2};
+
+// The nearest-neighbour visit without frames, by rate and counting; the
+// uncounted visit of a plan with a compiled pitch takes that instantiation.
+const void *near_fast_kernel(int dim, bool unit, bool count, const int *pitch = nullptr)
 {
+    auto same = [&](const int *c) {
+        return pitch && pitch[0] == c[0] && pitch[1] == c[1] && pitch[2] == c[2];
+    };
+    if (!count && dim == 2 && same(kPitch2))
+        return unit ? (const void *)visit_fast_kernel<2, false, 1, true, false, kPitch2[0], kPitch2[1], 0>
+                    : (const void *)visit_fast_kernel<2, false, 1, false, false, kPitch2[0], kPitch2[1], 0>;
+    if (!count && dim == 3 && same(kPitch3))
+        return unit ? (const void *)visit_fast_kernel<3, false, 1, true, false, kPitch3[0], kPitch3[1], kPitch3[2]>
+                    : (const void *)visit_fast_kernel<3, false, 1, false, false, kPitch3[0], kPitch3[1], kPitch3[2]>;
     if (unit) return count ? near_fn<true, true>(dim) : near_fn<true, false>(dim);
     return count ? near_fn<false, true>(dim) : near_fn<false, false>(dim);
 }
@@ -125,8 +143,10 @@ hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
     const unsigned tiles = (unsigned)a.ntiles[0] * (unsigned)a.ntiles[1] *
                            (unsigned)a.ntiles[2];
     const int q = a.range > 1 ? a.range : 1;
+    int pitch[3];
+    region::box_pitch(a, dim, pitch);
     const void *fn = (q == 1 && !a.frames)
-                         ? near_fast_kernel(dim, a.unit_rate != 0, a.count_efficiency != 0)
+                         ? near_fast_kernel(dim, a.unit_rate != 0, a.count_efficiency != 0, pitch)
                          : fast_kernel(dim, q, a.frames != nullptr);
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {const_cast<VisitArgs *>(&a)};
@@ -145,10 +165,11 @@ hipError_t set_visit_fast_lds_limit(size_t bytes)
                 if (e != hipSuccess) return e;
             }
     for (int dim = 1; dim <= 3; ++dim)
-        for (int v = 0; v < 4; ++v) {
-            const hipError_t e = hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)bytes);
+        for (int v = 0; v < 8; ++v) {
+            const int *pitch = (v & 4) ? (dim == 2 ? kPitch2 : dim == 3 ? kPitch3 : nullptr) : nullptr;
+            const hipError_t e =
+                hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2, pitch),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
             if (e != hipSuccess) return e;
         }
     return hipSuccess;
