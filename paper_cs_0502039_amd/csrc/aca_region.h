@@ -417,6 +417,47 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         for (int d = 0; d < DIM; ++d) in = in && q[d] >= Q && q[d] < Q + rin[d];
         return in;
     };
+    // The same tests as arithmetic, without a branch per condition: a cell is
+    // owned (simulated) iff no difference below is negative.
+    auto own_bits = [&](const int *q) {
+        int t = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) t |= (q[d] - olo[d]) | (ohi[d] - 1 - q[d]);
+        return t;
+    };
+    auto inner_bits = [&](const int *q) {
+        int t = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) t |= (q[d] - Q) | (Q + rin[d] - 1 - q[d]);
+        return t;
+    };
+    // Simulated cell number j in [0, nin) (row-major over the region without
+    // its ring) -> box coordinates, by reciprocal multiplies (exact for
+    // j < 2^16), and box index of box coordinates.
+    const int nin = rin[0] * rin[1] * rin[2];
+    const uint32_t imagic0 = rin[0] > 1 ? 0xFFFFFFFFu / (uint32_t)rin[0] + 1u : 0u;
+    const uint32_t imagic1 = rin[1] > 1 ? 0xFFFFFFFFu / (uint32_t)rin[1] + 1u : 0u;
+    auto inner_coords = [&](int j, int *q) {
+        if (DIM == 1) {
+            q[0] = j + Q;
+            q[1] = 0;
+            q[2] = 0;
+            return;
+        }
+        const int row = rin[0] > 1 ? (int)__umulhi((uint32_t)j, imagic0) : j;
+        q[0] = j - (int)__umul24((uint32_t)row, (uint32_t)rin[0]) + Q;
+        if (DIM == 2) {
+            q[1] = row + Q;
+            q[2] = 0;
+        } else {
+            const int pl = rin[1] > 1 ? (int)__umulhi((uint32_t)row, imagic1) : row;
+            q[1] = row - (int)__umul24((uint32_t)pl, (uint32_t)rin[1]) + Q;
+            q[2] = pl + Q;
+        }
+    };
+    auto box_index = [&](const int *q) {
+        return q[0] + P1 * q[1] + (DIM > 2 ? P12 * q[2] : 0);
+    };
     constexpr int U = 4;    // cells per thread in flight in the load loop
 
     // ---- load the region box from the snapshot; note whether any owned
@@ -436,19 +477,20 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             const int j = j0 + u * nthreads;
             int q[3];
             decode(min(j, boxp - 1), q);
-            ok[u] = j < boxp && q[0] < rb[0] && q[1] < rb[1] && q[2] < rb[2];
-            inn[u] = is_inner(q);
-            own[u] = is_own(q);
-            gi[u] = gidx_at(q);
+            // cells of the pitch beyond a ragged region's box read the box's
+            // last cell along that direction (a valid address) and are not kept
+            int qc[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) qc[d] = min(q[d], rb[d] - 1);
+            ok[u] = (j < boxp) & (q[0] < rb[0]) & (q[1] < rb[1]) & (q[2] < rb[2]);
+            inn[u] = inner_bits(q) >= 0;
+            own[u] = own_bits(q) >= 0;
+            gi[u] = gidx_at(qc);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            key[u] = 0;
-            tb[u] = 0;
-            if (ok[u]) {
-                key[u] = io.key_in[gi[u]];
-                tb[u] = io.time_in[gi[u]];
-            }
+            key[u] = io.key_in[gi[u]];
+            tb[u] = io.time_in[gi[u]];
         }
         if constexpr (COUNT) {
 #pragma unroll
@@ -459,16 +501,16 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!ok[u]) continue;
-            const int bi = j0 + u * nthreads;
-            ts[bi] = (uint64_t)tb[u] | ((key[u] & 1ull) << 63);
-            // a ring cell carries a claim that is never cleared: a re-test
-            // that finds it enabled can never list it
-            nl[bi] = inn[u] ? (uint32_t)(key[u] >> 32) : kClaim;
-            if (inn[u]) {
+            const bool mine = ok[u] & own[u];
+            due |= mine & ((uint64_t)tb[u] < a.final_bits);
+            tmin_own = (mine & ((uint64_t)tb[u] < tmin_own)) ? (uint64_t)tb[u] : tmin_own;
+            if (ok[u]) {
+                const int bi = j0 + u * nthreads;
+                ts[bi] = (uint64_t)tb[u] | ((key[u] & 1ull) << 63);
+                // a ring cell carries a claim that is never cleared: a re-test
+                // that finds it enabled can never list it
+                nl[bi] = inn[u] ? (uint32_t)(key[u] >> 32) : kClaim;
                 fl[bi] = 0;
-                due = due || (own[u] && (uint64_t)tb[u] < a.final_bits);
-                if (own[u] && (uint64_t)tb[u] < tmin_own) tmin_own = (uint64_t)tb[u];
             }
         }
     }
@@ -556,31 +598,39 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // wavefront for all of them; nearest neighbours only)
     constexpr int US = Q == 1 ? 4 : 1;   // a wider reach has no registers to spare
     uint32_t cnt_scan_own = 0;   // owned cells this lane listed
-    for (int base = tid - lane; base < boxp; base += US * nthreads) {
+    for (int base = tid - lane; base < nin; base += US * nthreads) {
         bool en[US], owned[US];
         int cell[US];
 #pragma unroll
         for (int u = 0; u < US; ++u) {
             const int j = base + u * nthreads + lane;
-            const int bi = min(j, boxp - 1);
+            int q[3];
+            inner_coords(min(j, nin - 1), q);
+            const int bi = box_index(q);
             cell[u] = bi;
             en[u] = false;
-            int q[3];
-            decode(bi, q);
-            owned[u] = is_own(q);
-            if (Q > 1 && j < boxp && is_inner(q)) {
+            owned[u] = own_bits(q) >= 0;
+            if (Q > 1 && j < nin) {
                 const uint64_t wc = ldw(&ts[bi]);
                 bool tie = false;
                 en[u] = enabled_q(bi, wc, tie);
                 if (tie) en[u] = exact_q(bi, q, wc);
                 ++my_checks;
-            } else if (Q == 1 && j < boxp && is_inner(q)) {
+            } else if (Q == 1 && j < nin) {
                 const uint64_t wc = ldw(&ts[bi]);
                 uint64_t tn[Z];
                 double tmin = horizon_t;
+                // with compiled pitches: one base register, non-negative
+                // constant offsets
+                constexpr int omin1 = kConstPitch ? -(DIM > 2 ? CP0 * CP1 : (DIM > 1 ? CP0 : 1)) : 0;
+                int sb = bi;
+                if constexpr (kConstPitch) {
+                    sb = bi + omin1;
+                    __asm__("" : "+v"(sb));
+                }
 #pragma unroll
                 for (int k = 0; k < Z; ++k) {
-                    tn[k] = ldw(&ts[bi + off(1 + k)]);
+                    tn[k] = ldw(&ts[kConstPitch ? sb + (off(1 + k) - omin1) : bi + off(1 + k)]);
                     tmin = __builtin_fmin(tmin, time_of(tn[k]));
                 }
                 // below the least of the horizon and the neighbour times; a
@@ -868,56 +918,55 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     }  // own_due
 
     // ---- merge owned copies and moved ghost copies; find due owned cells.
-    // A step reads the input keys of all its cells before it issues any merge
-    // atomic (reads, stores and atomics complete in order on one counter, so a
-    // read issued after atomics waits for them) and keeps only the keys: the
-    // cells' indices and flags are computed again, from an index the compiler
-    // cannot see through, when the keys are used.  For nearest neighbours, 12
-    // cells per thread cover a whole region in one step at the default tiles
-    // (4884 box cells for 512 threads in 2D, 9216 for 1024 in 3D).
+    // The merge walks the simulated cells only (the frozen ring is never
+    // merged).  A step first computes the box and global index of each of its
+    // cells and reads all their input keys, before it issues any merge atomic
+    // (reads, stores and atomics complete in order on one counter, so a read
+    // issued after atomics would wait for them); the indices stay in registers
+    // for the second pass.  For nearest neighbours, 12 cells per thread cover a
+    // whole region in one step at the default tiles (4608 simulated cells for
+    // 512 threads in 2D, 6776 for 1024 in 3D).
     constexpr int UM = Q == 1 ? 12 : 4;   // a wider reach has no registers to spare
-    auto opaque = [](int v) {
-        __asm__("" : "+v"(v));
-        return v;
-    };
     bool live = false;
-    for (int j0 = tid; j0 < boxp; j0 += UM * nthreads) {
+    for (int j0 = tid; j0 < nin; j0 += UM * nthreads) {
         unsigned long long key_in[UM];
+        int bix[UM];
+        uint32_t gix[UM];
+        bool ownx[UM];
 #pragma unroll
         for (int u = 0; u < UM; ++u) {
             const int j = j0 + u * nthreads;
             int q[3];
-            decode(min(j, boxp - 1), q);
-            key_in[u] = (j < boxp && is_inner(q)) ? io.key_in[gidx_at(q)] : 0ull;
+            inner_coords(min(j, nin - 1), q);
+            bix[u] = box_index(q);
+            gix[u] = gidx_at(q);
+            ownx[u] = own_bits(q) >= 0;
         }
-        const int jw = opaque(j0);
 #pragma unroll
         for (int u = 0; u < UM; ++u) {
-            // the box words are read before the cell is tested (the index is
-            // clamped into the box), so the reads of a step need no branches
-            const int bi = min(jw + u * nthreads, boxp - 1);
-            int q[3];
-            decode(bi, q);
+            // a step's last slots may lie past the region for a whole wavefront
+            const int wave_first = __builtin_amdgcn_readfirstlane(j0 - lane) + u * nthreads;
+            key_in[u] = wave_first < nin ? io.key_in[gix[u]] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < UM; ++u) {
+            const int bi = bix[u];
             const uint32_t n_copy = nl[bi] & kCountMask;   // a listed cell may be claimed
             const uint64_t wd = ts[bi];
             const uint32_t fc = fl[bi];
-            if (!(jw + u * nthreads < boxp && is_inner(q))) continue;
-            const bool own = is_own(q);
-            const uint32_t gi = gidx_at(q);
-            const uint32_t moved = n_copy - (uint32_t)(key_in[u] >> 32);
-            if (own) {
-                my_events += moved;
-                my_flips += fc;
-            } else {
-                my_ghost += moved;
-            }
-            if (own || moved != 0u) {
+            const bool valid = j0 + u * nthreads < nin;
+            const bool own = valid & ownx[u];
+            const uint32_t moved = valid ? n_copy - (uint32_t)(key_in[u] >> 32) : 0u;
+            my_events += own ? moved : 0u;
+            my_flips += own ? fc : 0u;
+            my_ghost += own ? 0u : moved;
+            live |= own & ((wd & kMask) < final_bits);
+            if (own | (moved != 0u)) {
                 const unsigned long long f = ((key_in[u] >> 1) & 0x7FFFFFFFull) + fc;
-                atomicMax(&io.key_out[gi],
+                atomicMax(&io.key_out[gix[u]],
                           ((unsigned long long)n_copy << 32) | (f << 1) | (wd >> 63));
-                atomicMax(&io.time_out[gi], (unsigned long long)(wd & kMask));
+                atomicMax(&io.time_out[gix[u]], (unsigned long long)(wd & kMask));
             }
-            if (own) live = live || (wd & kMask) < final_bits;
         }
     }
     atomicAdd(&ctr[6], (int)my_events);
