@@ -337,6 +337,14 @@ def bench_served(arena_gib: float, max_jobs: int, budget_ms: float, count: int) 
             "speedup_vs_plain": capacity / plain["jobs_per_s"],
             "plain": plain, "by_dim": by_dim,
             "capacity_spin_updates_per_s": st_c["events"] / wall_c,
+            # per server step of the capacity run: the persistent visits' device
+            # time, and the rest of the step (admission, pack/open/unpack
+            # launches, copies, the host's wait) -- the most that capturing a
+            # step's launches in a graph could save
+            "capacity_steps": st_c["steps"],
+            "capacity_kernel_ms_per_step": st_c["kernel_ms"] / max(1, st_c["steps"]),
+            "capacity_other_ms_per_step": (st_c["device_ms"] - st_c["kernel_ms"])
+            / max(1, st_c["steps"]),
             "rho_jobs_per_s": rho, "jobs_per_s": count / wall,
             "spin_updates_per_s": st["events"] / wall,
             "p50_ms": float(np.percentile(lat_ms, 50)),
