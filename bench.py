@@ -10,6 +10,8 @@ Prints one JSON line.  Besides the contract fields it carries
   roofline      the visit kernel: algorithmic bytes or per-arrival operations
                 per launch over the launch time measured with HIP events on the
                 launching stream (inside the library), against MI355X peaks;
+  other_configs the 64^2 and 256^3 lattices (automatic schedules): time per
+                advance, arrival rate, arithmetic-bound fraction, bit-exactness;
   cpu_baseline  the serial oracle timed on a bounded sample of the same workload
                 on one host core, the host's CPU model and core count, and an
                 all-core aggregate (one batch lattice per worker process);
@@ -354,6 +356,43 @@ def bench_served(arena_gib: float, max_jobs: int, budget_ms: float, count: int) 
             "arena_peak_gib": st["arena_peak"] / (1 << 30), "queued_peak": st["queued_peak"]}
 
 
+def bench_config(name: str, steps: int = 3) -> dict:
+    """One of the other single-lattice configurations (64^2 to T = 100, 256^3 to
+    T = 100) with the automatic schedule: best wall time per advance of several,
+    arrivals per second, the visit kernel's fraction of the arithmetic bound, and
+    the final state against the oracle's digest."""
+    import torch
+    from paper_cs_0502039_amd import aca, workloads
+    params = getattr(workloads, name)()
+    lat = aca.Lattice(params)
+    lat.init().advance(params["T"])
+    best = None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.init().advance(params["T"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    st = lat.stats()
+    out = {"workload": name, "ms_per_advance": best * 1e3, "events": st["events"],
+           "spin_updates_per_s": st["events"] / best, "launches": st["launches"],
+           "kernel_ms_per_launch": st["kernel_ms"] / st["launches"],
+           "alu_frac": st["events"] / (st["kernel_ms"] / 1e3)
+           / (VALU_LANE_OPS_PER_S / SLOTS_PER_EVENT),
+           "tuning": lat.tuning()}
+    gold_path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            gold = json.load(f)
+        out["bit_exact"] = digest(*lat.read()) == (gold["sha256_s"], gold["sha256_t"],
+                                                   gold["sha256_n"]) \
+            and gold["events"] == st["events"]
+    lat.close()
+    log(f"{name}: {best * 1e3:.2f} ms per advance, bit-exact {out.get('bit_exact')}")
+    return out
+
+
 def bench_served_plain(jobs) -> dict:
     """The plain path on the served mix: for each job in arrival order, its own
     state buffers, one aca_init + aca_advance on one stream, and the result read
@@ -662,6 +701,9 @@ def main() -> int:
     }
     lat.close()
     del lat
+    if args.only is None:
+        out["other_configs"] = {n: bench_config(n) for n in ("square_64", "cubic_256")
+                                if n != args.workload}
     if args.only is None and not args.no_batched:
         out["batched"] = bench_batched(args.steps, args.warmup, not args.no_autotune)
     if args.only is None and not args.no_served:
