@@ -262,8 +262,10 @@ aca_status aca_get_trace(const aca_lattice *lat, aca_launch_record *out, int32_t
 /* Autotuning on the caller's own work.  Every schedule yields the same
  * trajectory (Fig. 3.4's partition invariance), so the tuner advances the
  * real lattice: first a warm-up slice of dT/2 with the first candidate, then
- * one slice of dT per candidate, each timed on the device; it keeps the
- * candidate with the most arrivals per millisecond, installs it with
+ * two slices of dT/2 per candidate, the candidates in order and then in
+ * reverse order (so that a steady change of the work along the trajectory
+ * favours none), each timed on the device; it keeps the candidate with the
+ * most arrivals per millisecond over its two slices, installs it with
  * aca_set_tuning and leaves the lattice advanced by (n + 1/2) dT.  cands NULL
  * (or n = 0) uses the library's candidate set for the lattice's dimension.
  * rates (may be NULL) receives arrivals per millisecond of each candidate
@@ -418,11 +420,13 @@ aca_status aca_batch_advance(aca_batch *b, aca_lattice *const *lats, const doubl
 
 /* Batch autotuning for the members of dimension dim (as aca_tune): the batch
  * must be empty; lats[i] (initialised, horizons T[i]) are advanced slice by
- * slice, each slice a fraction frac of every lattice's remaining span to
- * T[i], one candidate per slice after a warm-up slice; the candidate with the
- * most arrivals per millisecond of device time becomes the batch's tuning for
- * dim.  Lattices of other dimensions advance too.  The lattices are left
- * detached, short of their horizons. */
+ * slice, each slice a fraction frac/2 of every lattice's span to T[i] at the
+ * start: a warm-up slice, then two slices per candidate, the candidates in
+ * order and then in reverse order ((n + 1/2) frac must not exceed 1; frac in
+ * (0, 0.5)); the candidate with the most arrivals per millisecond of device
+ * time over its two slices becomes the batch's tuning for dim.  Lattices of
+ * other dimensions advance too.  The lattices are left detached, short of
+ * their horizons. */
 aca_status aca_batch_tune(aca_batch *b, aca_lattice *const *lats, const double *T,
                           int32_t count, int32_t dim, const aca_tuning *cands, int32_t n,
                           double frac, void *stream, int32_t *best, double *rates,

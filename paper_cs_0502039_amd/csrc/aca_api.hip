@@ -178,8 +178,10 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->tile[0] = 8192; t->ghost[0] = 64;
         t->max_sweeps = 512; t->block = 256;
     } else if (p.dim == 2) {
-        t->tile[0] = 64; t->tile[1] = 56;
-        t->ghost[0] = 4; t->ghost[1] = 4;
+        // a 76 x 64 box (80.5 KB of LDS: two workgroups per CU); 5 ghost cells
+        // let a visit move its region one layer further than 4 at the same box
+        t->tile[0] = 64; t->tile[1] = 52;
+        t->ghost[0] = 5; t->ghost[1] = 5;
         t->max_sweeps = 32; t->block = 512;
     } else {
         // one 20x20x12 region fills most of a CU's LDS: 1024 threads keep
@@ -196,7 +198,8 @@ int tune_candidates(int dim, aca_tuning *out)
     // tile sides, ghost width, worklist rounds per visit
     static const int c1[][3] = {{8192, 64, 512}, {4096, 32, 256}, {16384, 64, 1024},
                                 {8192, 128, 1024}, {2048, 16, 128}};
-    static const int c2[][5] = {{64, 56, 4, 32, 0}, {64, 56, 4, 24, 0}, {64, 56, 4, 48, 0},
+    static const int c2[][5] = {{64, 52, 5, 32, 0}, {62, 54, 5, 32, 0}, {64, 56, 4, 32, 0},
+                                {64, 56, 4, 24, 0}, {64, 56, 4, 48, 0},
                                 {64, 48, 3, 32, 0}, {48, 48, 4, 32, 0}, {96, 40, 4, 32, 0},
                                 {64, 64, 3, 32, 0}, {32, 32, 2, 16, 0}, {64, 56, 2, 16, 0},
                                 {56, 56, 4, 32, 0}};
@@ -912,17 +915,25 @@ ACA_EXPORT aca_status aca_tune(aca_lattice *lat, const aca_tuning *cands, int32_
     }
     aca_status st = aca_set_tuning(lat, &cands[0]);
     if (st == ACA_OK) st = aca_advance(lat, lat->last_T + 0.5 * dT, stream);
-    double best_rate = -1.0;
-    int32_t best_k = 0;
-    for (int32_t k = 0; k < n && st == ACA_OK; ++k) {
+    // Each candidate runs two slices of dT/2, the candidates in order and then
+    // in reverse order, so that a steady drift of the work per unit of time
+    // along the trajectory favours none of them.
+    std::vector<double> ev(n, 0.0), ms(n, 0.0);
+    for (int32_t j = 0; j < 2 * n && st == ACA_OK; ++j) {
+        const int32_t k = j < n ? j : 2 * n - 1 - j;
         st = aca_set_tuning(lat, &cands[k]);
         if (st != ACA_OK) break;
         const uint64_t ev0 = lat->stats.events;
         const double ms0 = lat->stats.device_ms;
-        st = aca_advance(lat, lat->last_T + dT, stream);
+        st = aca_advance(lat, lat->last_T + 0.5 * dT, stream);
         if (st != ACA_OK) break;
-        const double ms = lat->stats.device_ms - ms0;
-        const double rate = ms > 0.0 ? (double)(lat->stats.events - ev0) / ms : 0.0;
+        ev[k] += (double)(lat->stats.events - ev0);
+        ms[k] += lat->stats.device_ms - ms0;
+    }
+    double best_rate = -1.0;
+    int32_t best_k = 0;
+    for (int32_t k = 0; k < n && st == ACA_OK; ++k) {
+        const double rate = ms[k] > 0.0 ? ev[k] / ms[k] : 0.0;
         if (rates) rates[k] = rate;
         if (rate > best_rate) {
             best_rate = rate;

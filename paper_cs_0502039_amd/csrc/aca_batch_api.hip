@@ -651,28 +651,35 @@ ACA_EXPORT aca_status aca_batch_tune(aca_batch *b, aca_lattice *const *lats, con
     const aca_tuning keep = b->tun[dim];
     std::vector<double> start(count), h(count);
     for (int32_t i = 0; i < count; ++i) start[i] = lats[i]->last_T;
-    // slice s ends at start + (s + 1) frac (T - start); slice 0 is the warm-up
+    // slice s ends at start + (s + 1) frac / 2 (T - start); slice 0 is the
+    // warm-up, then each candidate runs two slices, the candidates in order and
+    // then in reverse order (a steady drift along the trajectories favours none)
     auto slice = [&](int s) -> aca_status {
         for (int32_t i = 0; i < count; ++i) {
-            h[i] = start[i] + (double)(s + 1) * frac * (T[i] - start[i]);
+            h[i] = start[i] + (double)(s + 1) * 0.5 * frac * (T[i] - start[i]);
             h[i] = std::min(std::max(h[i], lats[i]->last_T), T[i]);
         }
         return aca_batch_advance(b, lats, h.data(), count, stream);
     };
-    if (n + 1 > (int32_t)(1.0 / frac))
-        return fail(ACA_EINVAL, "%d candidates need (n + 1) frac <= 1", n);
+    if ((2 * n + 1) * frac > 2.0)
+        return fail(ACA_EINVAL, "%d candidates need (n + 1/2) frac <= 1", n);
     aca_status st = aca_batch_set_tuning(b, dim, &cands[0]);
     if (st == ACA_OK) st = slice(0);
-    double best_rate = -1.0;
-    int32_t best_k = 0;
-    for (int32_t k = 0; k < n && st == ACA_OK; ++k) {
+    std::vector<double> ev(n, 0.0), ms(n, 0.0);
+    for (int32_t j = 0; j < 2 * n && st == ACA_OK; ++j) {
+        const int32_t k = j < n ? j : 2 * n - 1 - j;
         st = aca_batch_set_tuning(b, dim, &cands[k]);
         if (st != ACA_OK) break;
         const aca_batch_stats s0 = b->stats;
-        st = slice(k + 1);
+        st = slice(j + 1);
         if (st != ACA_OK) break;
-        const double ms = b->stats.device_ms - s0.device_ms;
-        const double rate = ms > 0.0 ? (double)(b->stats.events - s0.events) / ms : 0.0;
+        ev[k] += (double)(b->stats.events - s0.events);
+        ms[k] += b->stats.device_ms - s0.device_ms;
+    }
+    double best_rate = -1.0;
+    int32_t best_k = 0;
+    for (int32_t k = 0; k < n && st == ACA_OK; ++k) {
+        const double rate = ms[k] > 0.0 ? ev[k] / ms[k] : 0.0;
         if (rates) rates[k] = rate;
         if (rate > best_rate) {
             best_rate = rate;

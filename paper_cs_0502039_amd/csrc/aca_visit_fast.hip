@@ -70,8 +70,11 @@ const void *near_fn(int dim)
 }
 
 // Box pitches compiled as constants: the default region of a 2D lattice (a
-// 64 x 56 tile with 4 ghost cells a side) and of a 3D one (20 x 20 x 12 with 1).
-constexpr int kPitch2[3] = {64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 1};
+// 64 x 52 tile with 5 ghost cells a side), the other 2D box the autotuner
+// often picks (64 x 56 with 4, or 62 x 54 with 5), and the default 3D region
+// (20 x 20 x 12 with 1).
+constexpr int kPitch2[3] = {64 + 2 * 5 + 2, 52 + 2 * 5 + 2, 1};
+constexpr int kPitch2b[3] = {64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 1};
 constexpr int kPitch3[3] = {20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 12 + 2 * 1 + 2};
 
 // The nearest-neighbour visit without frames, by rate and counting; the
@@ -84,6 +87,9 @@ const void *near_fast_kernel(int dim, bool unit, bool count, const int *pitch = 
     if (!count && dim == 2 && same(kPitch2))
         return unit ? (const void *)visit_fast_kernel<2, false, 1, true, false, kPitch2[0], kPitch2[1], 0>
                     : (const void *)visit_fast_kernel<2, false, 1, false, false, kPitch2[0], kPitch2[1], 0>;
+    if (!count && dim == 2 && same(kPitch2b))
+        return unit ? (const void *)visit_fast_kernel<2, false, 1, true, false, kPitch2b[0], kPitch2b[1], 0>
+                    : (const void *)visit_fast_kernel<2, false, 1, false, false, kPitch2b[0], kPitch2b[1], 0>;
     if (!count && dim == 3 && same(kPitch3))
         return unit ? (const void *)visit_fast_kernel<3, false, 1, true, false, kPitch3[0], kPitch3[1], kPitch3[2]>
                     : (const void *)visit_fast_kernel<3, false, 1, false, false, kPitch3[0], kPitch3[1], kPitch3[2]>;
@@ -165,8 +171,10 @@ hipError_t set_visit_fast_lds_limit(size_t bytes)
                 if (e != hipSuccess) return e;
             }
     for (int dim = 1; dim <= 3; ++dim)
-        for (int v = 0; v < 8; ++v) {
-            const int *pitch = (v & 4) ? (dim == 2 ? kPitch2 : dim == 3 ? kPitch3 : nullptr) : nullptr;
+        for (int v = 0; v < 12; ++v) {
+            const int *pitch = (v & 8) ? (dim == 2 ? kPitch2b : nullptr)
+                               : (v & 4) ? (dim == 2 ? kPitch2 : dim == 3 ? kPitch3 : nullptr)
+                                         : nullptr;
             const hipError_t e =
                 hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2, pitch),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
