@@ -184,10 +184,11 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->ghost[0] = 5; t->ghost[1] = 5;
         t->max_sweeps = 32; t->block = 512;
     } else {
-        // one 20x20x12 region fills most of a CU's LDS: 1024 threads keep
-        // sixteen wavefronts per CU; later rounds of a 3D visit hold few
-        // cells (a frozen ring one ghost cell away), so visits stop at 12
-        t->tile[0] = 20; t->tile[1] = 20; t->tile[2] = 12;
+        // one 20x20x14 region (24x24x18 box, 158 KB) fills a CU's LDS: 1024
+        // threads keep sixteen wavefronts per CU; later rounds of a 3D visit
+        // hold few cells (a frozen ring one ghost cell away), so visits stop
+        // at 12
+        t->tile[0] = 20; t->tile[1] = 20; t->tile[2] = 14;
         t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
         t->max_sweeps = 12; t->block = 1024;
     }
@@ -204,9 +205,9 @@ int tune_candidates(int dim, aca_tuning *out)
                                 {64, 64, 3, 32, 0}, {32, 32, 2, 16, 0}, {64, 56, 2, 16, 0},
                                 {56, 56, 4, 32, 0}};
     // tile sides, ghost, rounds, threads
-    static const int c3[][6] = {{20, 20, 12, 1, 16, 1024}, {16, 16, 8, 1, 16, 512},
-                                {16, 16, 16, 1, 16, 1024}, {20, 20, 12, 1, 12, 1024},
-                                {20, 20, 12, 1, 24, 1024}, {16, 16, 8, 1, 12, 512},
+    static const int c3[][6] = {{20, 20, 14, 1, 12, 1024}, {20, 20, 14, 1, 16, 1024},
+                                {18, 18, 12, 2, 16, 1024}, {20, 20, 12, 1, 12, 1024},
+                                {20, 20, 12, 1, 16, 1024}, {16, 16, 8, 1, 12, 512},
                                 {20, 16, 12, 1, 16, 1024}, {8, 8, 8, 1, 8, 512}};
     int n = 0;
     auto base = [&]() -> aca_tuning & {

@@ -71,11 +71,13 @@ const void *near_fn(int dim)
 
 // Box pitches compiled as constants: the default region of a 2D lattice (a
 // 64 x 52 tile with 5 ghost cells a side), the other 2D box the autotuner
-// often picks (64 x 56 with 4, or 62 x 54 with 5), and the default 3D region
-// (20 x 20 x 12 with 1).
+// often picks (64 x 56 with 4, or 62 x 54 with 5), the default 3D region
+// (20 x 20 x 14 with 1, or 18 x 18 x 12 with 2) and the earlier 3D default
+// (20 x 20 x 12 with 1, or 18 x 18 x 10 with 2).
 constexpr int kPitch2[3] = {64 + 2 * 5 + 2, 52 + 2 * 5 + 2, 1};
 constexpr int kPitch2b[3] = {64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 1};
 constexpr int kPitch3[3] = {20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 12 + 2 * 1 + 2};
+constexpr int kPitch3b[3] = {20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 14 + 2 * 1 + 2};
 
 // The nearest-neighbour visit without frames, by rate and counting; the
 // uncounted visit of a plan with a compiled pitch takes that instantiation.
@@ -93,6 +95,9 @@ const void *near_fast_kernel(int dim, bool unit, bool count, const int *pitch = 
     if (!count && dim == 3 && same(kPitch3))
         return unit ? (const void *)visit_fast_kernel<3, false, 1, true, false, kPitch3[0], kPitch3[1], kPitch3[2]>
                     : (const void *)visit_fast_kernel<3, false, 1, false, false, kPitch3[0], kPitch3[1], kPitch3[2]>;
+    if (!count && dim == 3 && same(kPitch3b))
+        return unit ? (const void *)visit_fast_kernel<3, false, 1, true, false, kPitch3b[0], kPitch3b[1], kPitch3b[2]>
+                    : (const void *)visit_fast_kernel<3, false, 1, false, false, kPitch3b[0], kPitch3b[1], kPitch3b[2]>;
     if (unit) return count ? near_fn<true, true>(dim) : near_fn<true, false>(dim);
     return count ? near_fn<false, true>(dim) : near_fn<false, false>(dim);
 }
@@ -172,7 +177,7 @@ hipError_t set_visit_fast_lds_limit(size_t bytes)
             }
     for (int dim = 1; dim <= 3; ++dim)
         for (int v = 0; v < 12; ++v) {
-            const int *pitch = (v & 8) ? (dim == 2 ? kPitch2b : nullptr)
+            const int *pitch = (v & 8) ? (dim == 2 ? kPitch2b : dim == 3 ? kPitch3b : nullptr)
                                : (v & 4) ? (dim == 2 ? kPitch2 : dim == 3 ? kPitch3 : nullptr)
                                          : nullptr;
             const hipError_t e =

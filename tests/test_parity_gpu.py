@@ -131,6 +131,40 @@ def test_result_independent_of_tiling(torch, params, tuning):
     assert st["events"] == ev
 
 
+# Region shapes whose box pitches the library compiles as constants (each
+# with a second tile/ghost pair of the same box), on lattices several tiles
+# wide with a ragged last tile along every direction and rate 1 and 0.37.
+COMPILED_PITCH_CASES = [
+    (workloads.lattice(2, (150, 121), 0.41, seed=81, T=6.0),
+     [dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
+      dict(tile=(62, 50), ghost=(6, 6), max_sweeps=40, block=512),
+      dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512),
+      dict(tile=(62, 54), ghost=(5, 5), max_sweeps=16, block=512)]),
+    (workloads.lattice(2, (131, 140), 0.3, "metropolis", h=0.2, seed=82, T=5.0, rate=0.37),
+     [dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
+      dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512)]),
+    (workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", h=0.1, init="plus", seed=83, T=4.0),
+     [dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+      dict(tile=(18, 18, 12), ghost=(2, 2, 2), max_sweeps=16, block=1024),
+      dict(tile=(20, 20, 12), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+      dict(tile=(18, 18, 10), ghost=(2, 2, 2), max_sweeps=16, block=1024)]),
+    (workloads.lattice(3, (45, 41, 33), 0.2, "glauber", seed=84, T=3.0, rate=0.37),
+     [dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+      dict(tile=(20, 20, 12), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
+]
+
+
+@pytest.mark.parametrize("params,tunings", COMPILED_PITCH_CASES,
+                         ids=lambda v: f"{v['dim']}d-{'x'.join(map(str, v['L']))}" if isinstance(v, dict) else "")
+def test_compiled_pitch_regions_match_oracle(torch, params, tunings):
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    for tuning in tunings:
+        say(f"compiled pitch {tuning} case {params['L']} rate {params['rate']}")
+        gs, gt, gn, st = gpu_run(params, params["T"], tuning=tuning)
+        assert_same_state((gs, gt, gn), (s, t, n), str(tuning))
+        assert st["events"] == ev and st["flips"] == fl
+
+
 def test_chunked_advance(torch):
     params = workloads.lattice(2, (150, 97), 0.42, "metropolis", h=-0.07, seed=21, T=30.0)
     s, t, n, ev, fl = oracle.simulate(params, 30.0)
