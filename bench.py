@@ -594,7 +594,18 @@ def main() -> int:
         # the tuner advances the real lattice slice by slice; the warm-up pass
         # then finishes it (same final state whichever schedule wins)
         lat.init()
-        tune = lat.tune(max(T / 20.0, 1e-3))
+        # a slice should span several launches: a slice's last launch is a
+        # partial one that costs nearly a whole launch, which would favour
+        # the candidates with fewer rounds per visit in short slices; five
+        # candidates of T/6 each leave a sixth of the horizon for the finish
+        cands = None
+        if params["dim"] == 2:
+            cands = [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40),
+                     dict(tile=(64, 60), ghost=(5, 5), max_sweeps=32),
+                     dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32),
+                     dict(tile=(62, 54), ghost=(5, 5), max_sweeps=32),
+                     dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32)]
+        tune = lat.tune(max(T / (6.0 if cands else 20.0), 1e-3), cands)
         lat.advance(T)
         log(f"autotuned: {tune['tuning']} (rates per ms "
             f"{[round(r) for r in tune['rates_per_ms']]})")

@@ -86,7 +86,8 @@ typedef struct aca_params {
  * for Fig. 3.4), only speed.  struct_size must be sizeof(aca_tuning).
  *  tile[d]    own cells of a workgroup tile along d (0 = automatic)
  *  ghost[d]   extra cells simulated on each side and discarded (-1 = auto)
- *  max_sweeps worklist rounds of a tile per visit (0 = automatic)
+ *  max_sweeps worklist rounds of a tile per visit (0 = automatic; larger
+ *             values than 255 run as 255)
  *  block      threads per workgroup, multiple of 64 up to 1024 (0 = auto) */
 typedef struct aca_tuning {
     uint32_t struct_size;

@@ -178,17 +178,17 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->tile[0] = 8192; t->ghost[0] = 64;
         t->max_sweeps = 512; t->block = 256;
     } else if (p.dim == 2) {
-        // a 76 x 64 box (80.5 KB of LDS: two workgroups per CU); 5 ghost cells
+        // a 76 x 72 box (78 KB of LDS: two workgroups per CU); 5 ghost cells
         // let a visit move its region one layer further than 4 at the same box
-        t->tile[0] = 64; t->tile[1] = 52;
+        t->tile[0] = 64; t->tile[1] = 60;
         t->ghost[0] = 5; t->ghost[1] = 5;
-        t->max_sweeps = 32; t->block = 512;
+        t->max_sweeps = 40; t->block = 512;
     } else {
-        // one 20x20x14 region (24x24x18 box, 158 KB) fills a CU's LDS: 1024
+        // one 20x20x16 region (24x24x20 box, 155 KB) fills a CU's LDS: 1024
         // threads keep sixteen wavefronts per CU; later rounds of a 3D visit
         // hold few cells (a frozen ring one ghost cell away), so visits stop
         // at 12
-        t->tile[0] = 20; t->tile[1] = 20; t->tile[2] = 14;
+        t->tile[0] = 20; t->tile[1] = 20; t->tile[2] = 16;
         t->ghost[0] = 1; t->ghost[1] = 1; t->ghost[2] = 1;
         t->max_sweeps = 12; t->block = 1024;
     }
@@ -199,15 +199,12 @@ int tune_candidates(int dim, aca_tuning *out)
     // tile sides, ghost width, worklist rounds per visit
     static const int c1[][3] = {{8192, 64, 512}, {4096, 32, 256}, {16384, 64, 1024},
                                 {8192, 128, 1024}, {2048, 16, 128}};
-    static const int c2[][5] = {{64, 52, 5, 32, 0}, {62, 54, 5, 32, 0}, {64, 56, 4, 32, 0},
-                                {64, 56, 4, 24, 0}, {64, 56, 4, 48, 0},
-                                {64, 48, 3, 32, 0}, {48, 48, 4, 32, 0}, {96, 40, 4, 32, 0},
-                                {64, 64, 3, 32, 0}, {32, 32, 2, 16, 0}, {64, 56, 2, 16, 0},
-                                {56, 56, 4, 32, 0}};
+    static const int c2[][5] = {{64, 60, 5, 40, 0}, {64, 60, 5, 32, 0}, {64, 52, 5, 32, 0},
+                                {62, 54, 5, 32, 0}, {64, 56, 4, 32, 0}, {32, 32, 2, 16, 0}};
     // tile sides, ghost, rounds, threads
-    static const int c3[][6] = {{20, 20, 14, 1, 12, 1024}, {20, 20, 14, 1, 16, 1024},
-                                {18, 18, 12, 2, 16, 1024}, {20, 20, 12, 1, 12, 1024},
-                                {20, 20, 12, 1, 16, 1024}, {16, 16, 8, 1, 12, 512},
+    static const int c3[][6] = {{20, 20, 16, 1, 12, 1024}, {20, 20, 16, 1, 16, 1024},
+                                {20, 20, 14, 1, 12, 1024}, {18, 18, 14, 2, 16, 1024},
+                                {20, 20, 12, 1, 12, 1024}, {16, 16, 8, 1, 12, 512},
                                 {20, 16, 12, 1, 16, 1024}, {8, 8, 8, 1, 8, 512}};
     int n = 0;
     auto base = [&]() -> aca_tuning & {
@@ -257,8 +254,8 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
     if (t.block % 64 != 0 || t.block < 64 || t.block > 1024)
         return fail(ACA_EINVAL, "block %d must be a multiple of 64 in [64, 1024]", t.block);
     // a cell applies at most one arrival per sweep; per-visit flip counts are
-    // kept in 16 bits
-    t.max_sweeps = std::min(t.max_sweeps, 65535);
+    // kept in 8 bits
+    t.max_sweeps = std::min(t.max_sweeps, 255);
 
     aca::VisitArgs &a = plan->a;
     memset(&a, 0, sizeof a);
@@ -276,6 +273,12 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
                 a.span[d] = 1; a.tile[d] = L; a.ntiles[d] = 1; a.ghost[d] = 0;
             } else {
                 a.span[d] = 0;
+                // an automatic tile that would leave too little lattice for
+                // its ghost cells is evened out over the same number of tiles
+                if (lat->tun.tile[d] <= 0 && (L - t.tile[d]) / 2 < t.ghost[d]) {
+                    const int k = (L + t.tile[d] - 1) / t.tile[d];
+                    t.tile[d] = (L + k - 1) / k;
+                }
                 a.tile[d] = t.tile[d];
                 a.ntiles[d] = (L + t.tile[d] - 1) / t.tile[d];
                 // keep the simulated region within one period of the lattice

@@ -134,7 +134,7 @@ aca_status member_plan(const aca_batch *b, const aca_lattice *lat, double T, aca
         if (u.ghost[d] >= 0) t.ghost[d] = u.ghost[d];
     }
     if (u.max_sweeps > 0) t.max_sweeps = u.max_sweeps;
-    t.max_sweeps = std::min(t.max_sweeps, 65535);
+    t.max_sweeps = std::min(t.max_sweeps, 255);
     memset(a, 0, sizeof *a);
     for (int d = 0; d < 3; ++d) {
         if (d < p.dim) {

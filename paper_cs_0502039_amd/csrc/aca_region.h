@@ -257,9 +257,17 @@ __host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim, const
     p.ts_off = (p.tab_off + 4 * (size_t)(pitch[0] + pitch[1] + pitch[2]) + 7) & ~(size_t)7;
     p.ts_off += 8 * guard;
     p.n_off = p.ts_off + 8 * (boxp + guard);                    // uint32 n[boxp] | claim
-    p.f_off = p.n_off + 4 * boxp;                               // uint16 f[boxp]
-    p.list_off = (p.f_off + 2 * boxp + 3) & ~(size_t)3;
-    p.list_cap = (size_t)inner / 2 + 2;                         // uint16 list[2][cap]
+    p.f_off = p.n_off + 4 * boxp;                               // uint8 f[boxp]
+    p.list_off = (p.f_off + boxp + 3) & ~(size_t)3;
+    // uint16 list[2][cap].  A list never holds two neighbours, so half the
+    // simulated cells always fit; fewer are enabled at once in practice (a
+    // fifth of them at a random state in 2D, a seventh in 3D, and about half
+    // that later), so the lists hold a quarter (2D) or a fifth (3D) plus
+    // slack, and a cell that finds its list full is left for the next visit's
+    // scan (postponing an enabled arrival never changes the result)
+    const size_t half = (size_t)inner / 2 + 2;
+    const size_t part = (size_t)inner / (dim == 1 ? 2 : (dim == 2 ? 4 : 5)) + 64;
+    p.list_cap = part < half ? part : half;
     p.total = (p.list_off + 4 * p.list_cap + 15) & ~(size_t)15;
     return p;
 }
@@ -353,7 +361,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     uint32_t *tz = ty + pitch[1];
     uint64_t *ts = reinterpret_cast<uint64_t *>(lds + plan.ts_off);
     uint32_t *nl = reinterpret_cast<uint32_t *>(lds + plan.n_off);
-    uint16_t *fl = reinterpret_cast<uint16_t *>(lds + plan.f_off);
+    uint8_t *fl = reinterpret_cast<uint8_t *>(lds + plan.f_off);   // flips this visit
     uint16_t *lists = reinterpret_cast<uint16_t *>(lds + plan.list_off);
     const int cap = (int)plan.list_cap;
     int *sizes = ctr;        // [0..2] list lengths, rotating over rounds
@@ -663,7 +671,8 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
             b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
 #pragma unroll
             for (int u = 0; u < US; ++u) {
-                if (en[u]) lists[b0 + lanes_below(m[u])] = (uint16_t)cell[u];
+                const int at = b0 + lanes_below(m[u]);
+                if (en[u] && at < cap) lists[at] = (uint16_t)cell[u];
                 b0 += (int)__popcll(m[u]);
             }
         }
@@ -676,7 +685,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
 
     // ---- worklist rounds
     for (int rnd = 0; rnd < a.max_sweeps; ++rnd) {
-        const int sz = sizes[rnd % 3];
+        const int sz = min(sizes[rnd % 3], cap);   // appends past the cap were dropped
         if (sz == 0) break;
         ++rounds;
         if (tid == 0) sizes[(rnd + 2) % 3] = 0;
@@ -713,7 +722,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                                        gidx, tnow, __builtin_fmin(tnext, final_t),
                                        (wnew >> 63) ? (int8_t)-1 : (int8_t)1);
                     nl[bi] = kn + 1u;
-                    fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
+                    fl[bi] = (uint8_t)(fl[bi] + (flip ? 1u : 0u));
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                     stw(&ts[bi], wnew);
                 }
@@ -744,7 +753,8 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                         int b0 = 0;
                         if (lane == 0) b0 = atomicAdd(next_size, (int)__popcll(mk));
                         b0 = __builtin_amdgcn_readfirstlane(b0);  // lane 0 is active
-                        if (want) lnext[b0 + lanes_below(mk)] = (uint16_t)xb;
+                        const int at = b0 + lanes_below(mk);
+                        if (want && at < cap) lnext[at] = (uint16_t)xb;
                     }
                 }
                 continue;
@@ -799,7 +809,7 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                     capture_frames(a.frames, a.frame_dt, a.frame_k0, a.nframes, a.n_cells, gidx, tnow, __builtin_fmin(tnext, final_t),
                                    (wnew >> 63) ? (int8_t)-1 : (int8_t)1);
                 nl[bi] = kn + 1u;
-                fl[bi] = (uint16_t)(fl[bi] + (flip ? 1u : 0u));
+                fl[bi] = (uint8_t)(fl[bi] + (flip ? 1u : 0u));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 stw(&ts[bi], wnew);
                 W[0] = wnew;
@@ -908,11 +918,20 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
                 if (active) {
                     const int spare = (int)(lcur - lists) + start + lane;
                     const int nbase = (int)(lnext - lists);
+                    if (b0 + total <= cap) {   // the common case: all entries fit
 #pragma unroll
-                    for (int s = 0; s <= Z; ++s) {
-                        const int below = lanes_below(mk[s]);
-                        lists[take[s] ? nbase + b0 + below : spare] = (uint16_t)cb[s];
-                        b0 += (int)__popcll(mk[s]);
+                        for (int s = 0; s <= Z; ++s) {
+                            const int below = lanes_below(mk[s]);
+                            lists[take[s] ? nbase + b0 + below : spare] = (uint16_t)cb[s];
+                            b0 += (int)__popcll(mk[s]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int s = 0; s <= Z; ++s) {
+                            const int at = b0 + lanes_below(mk[s]);
+                            lists[(take[s] && at < cap) ? nbase + at : spare] = (uint16_t)cb[s];
+                            b0 += (int)__popcll(mk[s]);
+                        }
                     }
                 }
             }

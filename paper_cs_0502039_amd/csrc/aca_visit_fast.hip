@@ -69,35 +69,53 @@ const void *near_fn(int dim)
     }
 }
 
-// Box pitches compiled as constants: the default region of a 2D lattice (a
-// 64 x 52 tile with 5 ghost cells a side), the other 2D box the autotuner
-// often picks (64 x 56 with 4, or 62 x 54 with 5), the default 3D region
-// (20 x 20 x 14 with 1, or 18 x 18 x 12 with 2) and the earlier 3D default
-// (20 x 20 x 12 with 1, or 18 x 18 x 10 with 2).
-constexpr int kPitch2[3] = {64 + 2 * 5 + 2, 52 + 2 * 5 + 2, 1};
-constexpr int kPitch2b[3] = {64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 1};
-constexpr int kPitch3[3] = {20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 12 + 2 * 1 + 2};
-constexpr int kPitch3b[3] = {20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 14 + 2 * 1 + 2};
+// Box pitches compiled as constants (own tile + 2 ghost + 2 ring cells a
+// side).  2D: 76 x 72 (the default 64 x 60 tile with 5 ghost cells), 76 x 64
+// (64 x 52 with 5) and 74 x 66 (64 x 56 with 4, or 62 x 54 with 5); 3D:
+// 24 x 24 x 20 (the default 20 x 20 x 16 tile with 1, or 18 x 18 x 14 with 2)
+// and 24 x 24 x 18 (20 x 20 x 14 with 1).
+template <int P0, int P1, int P2>
+struct CompiledPitch {
+    static constexpr int dim = P2 > 1 ? 3 : 2;
+    static bool matches(const int *pitch)
+    {
+        return pitch[0] == P0 && pitch[1] == P1 && pitch[2] == (P2 > 1 ? P2 : 1);
+    }
+    static const void *kernel(bool unit)
+    {
+        return unit ? (const void *)visit_fast_kernel<dim, false, 1, true, false, P0, P1, P2>
+                    : (const void *)visit_fast_kernel<dim, false, 1, false, false, P0, P1, P2>;
+    }
+};
+using Pitch2a = CompiledPitch<64 + 2 * 5 + 2, 60 + 2 * 5 + 2, 0>;
+using Pitch2b = CompiledPitch<64 + 2 * 5 + 2, 52 + 2 * 5 + 2, 0>;
+using Pitch2c = CompiledPitch<64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 0>;
+using Pitch3a = CompiledPitch<20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 16 + 2 * 1 + 2>;
+using Pitch3b = CompiledPitch<20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 14 + 2 * 1 + 2>;
+
+// The uncounted nearest-neighbour visit compiled for `pitch`, or NULL.
+const void *compiled_pitch_kernel(int dim, bool unit, const int *pitch)
+{
+    if (!pitch) return nullptr;
+    if (dim == 2) {
+        if (Pitch2a::matches(pitch)) return Pitch2a::kernel(unit);
+        if (Pitch2b::matches(pitch)) return Pitch2b::kernel(unit);
+        if (Pitch2c::matches(pitch)) return Pitch2c::kernel(unit);
+    } else if (dim == 3) {
+        if (Pitch3a::matches(pitch)) return Pitch3a::kernel(unit);
+        if (Pitch3b::matches(pitch)) return Pitch3b::kernel(unit);
+    }
+    return nullptr;
+}
 
 // The nearest-neighbour visit without frames, by rate and counting; the
 // uncounted visit of a plan with a compiled pitch takes that instantiation.
 const void *near_fast_kernel(int dim, bool unit, bool count, const int *pitch = nullptr)
 {
-    auto same = [&](const int *c) {
-        return pitch && pitch[0] == c[0] && pitch[1] == c[1] && pitch[2] == c[2];
-    };
-    if (!count && dim == 2 && same(kPitch2))
-        return unit ? (const void *)visit_fast_kernel<2, false, 1, true, false, kPitch2[0], kPitch2[1], 0>
-                    : (const void *)visit_fast_kernel<2, false, 1, false, false, kPitch2[0], kPitch2[1], 0>;
-    if (!count && dim == 2 && same(kPitch2b))
-        return unit ? (const void *)visit_fast_kernel<2, false, 1, true, false, kPitch2b[0], kPitch2b[1], 0>
-                    : (const void *)visit_fast_kernel<2, false, 1, false, false, kPitch2b[0], kPitch2b[1], 0>;
-    if (!count && dim == 3 && same(kPitch3))
-        return unit ? (const void *)visit_fast_kernel<3, false, 1, true, false, kPitch3[0], kPitch3[1], kPitch3[2]>
-                    : (const void *)visit_fast_kernel<3, false, 1, false, false, kPitch3[0], kPitch3[1], kPitch3[2]>;
-    if (!count && dim == 3 && same(kPitch3b))
-        return unit ? (const void *)visit_fast_kernel<3, false, 1, true, false, kPitch3b[0], kPitch3b[1], kPitch3b[2]>
-                    : (const void *)visit_fast_kernel<3, false, 1, false, false, kPitch3b[0], kPitch3b[1], kPitch3b[2]>;
+    if (!count) {
+        const void *f = compiled_pitch_kernel(dim, unit, pitch);
+        if (f) return f;
+    }
     if (unit) return count ? near_fn<true, true>(dim) : near_fn<true, false>(dim);
     return count ? near_fn<false, true>(dim) : near_fn<false, false>(dim);
 }
@@ -176,15 +194,22 @@ hipError_t set_visit_fast_lds_limit(size_t bytes)
                 if (e != hipSuccess) return e;
             }
     for (int dim = 1; dim <= 3; ++dim)
-        for (int v = 0; v < 12; ++v) {
-            const int *pitch = (v & 8) ? (dim == 2 ? kPitch2b : dim == 3 ? kPitch3b : nullptr)
-                               : (v & 4) ? (dim == 2 ? kPitch2 : dim == 3 ? kPitch3 : nullptr)
-                                         : nullptr;
-            const hipError_t e =
-                hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2, pitch),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        for (int v = 0; v < 4; ++v) {
+            const hipError_t e = hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)bytes);
             if (e != hipSuccess) return e;
         }
+    const void *compiled[] = {Pitch2a::kernel(false), Pitch2a::kernel(true),
+                              Pitch2b::kernel(false), Pitch2b::kernel(true),
+                              Pitch2c::kernel(false), Pitch2c::kernel(true),
+                              Pitch3a::kernel(false), Pitch3a::kernel(true),
+                              Pitch3b::kernel(false), Pitch3b::kernel(true)};
+    for (const void *f : compiled) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 

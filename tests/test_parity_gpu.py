@@ -135,28 +135,64 @@ def test_result_independent_of_tiling(torch, params, tuning):
 # with a second tile/ghost pair of the same box), on lattices several tiles
 # wide with a ragged last tile along every direction and rate 1 and 0.37.
 COMPILED_PITCH_CASES = [
-    (workloads.lattice(2, (150, 121), 0.41, seed=81, T=6.0),
-     [dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
+    (workloads.lattice(2, (150, 131), 0.41, seed=81, T=6.0),
+     [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512),
+      dict(tile=(62, 58), ghost=(6, 6), max_sweeps=40, block=512),
+      dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
       dict(tile=(62, 50), ghost=(6, 6), max_sweeps=40, block=512),
       dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512),
       dict(tile=(62, 54), ghost=(5, 5), max_sweeps=16, block=512)]),
     (workloads.lattice(2, (131, 140), 0.3, "metropolis", h=0.2, seed=82, T=5.0, rate=0.37),
-     [dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
+     [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512),
+      dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
       dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512)]),
     (workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", h=0.1, init="plus", seed=83, T=4.0),
-     [dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024),
-      dict(tile=(18, 18, 12), ghost=(2, 2, 2), max_sweeps=16, block=1024),
-      dict(tile=(20, 20, 12), ghost=(1, 1, 1), max_sweeps=12, block=1024),
-      dict(tile=(18, 18, 10), ghost=(2, 2, 2), max_sweeps=16, block=1024)]),
-    (workloads.lattice(3, (45, 41, 33), 0.2, "glauber", seed=84, T=3.0, rate=0.37),
-     [dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024),
-      dict(tile=(20, 20, 12), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
+     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+      dict(tile=(18, 18, 14), ghost=(2, 2, 2), max_sweeps=16, block=1024),
+      dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+      dict(tile=(18, 18, 12), ghost=(2, 2, 2), max_sweeps=16, block=1024)]),
+    (workloads.lattice(3, (45, 41, 35), 0.2, "glauber", seed=84, T=3.0, rate=0.37),
+     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+      dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
+    # a state with every cell enabled at once where its neighbours' times are
+    # larger (a checkerboard of early and late times): the first scan's list
+    # holds half the simulated cells, past the list capacity, and the cells
+    # that do not fit wait for the next visit
+    (dict(workloads.lattice(2, (150, 131), 0.41, seed=85, T=6.0), checkerboard=True),
+     [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512)]),
+    (dict(workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", seed=86, T=3.0), checkerboard=True),
+     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
 ]
 
 
 @pytest.mark.parametrize("params,tunings", COMPILED_PITCH_CASES,
                          ids=lambda v: f"{v['dim']}d-{'x'.join(map(str, v['L']))}" if isinstance(v, dict) else "")
 def test_compiled_pitch_regions_match_oracle(torch, params, tunings):
+    params = dict(params)
+    if params.pop("checkerboard", False):
+        # start from the oracle's initial state with the pending times of one
+        # checkerboard colour pulled below every time of the other
+        s0, t0, n0 = oracle.init(params)
+        idx = np.indices(params["L"][::-1]).sum(axis=0).ravel()
+        t0 = np.where(idx % 2 == 0, t0 * 1e-3, t0 + 1.0)
+        T = params["T"]
+        s, t, n = s0.copy(), t0.copy(), n0.copy()
+        oracle.run(params, T, s, t, n)
+        for tuning in tunings:
+            say(f"compiled pitch {tuning} checkerboard case {params['L']}")
+            lat = aca.Lattice(params, tuning=tuning)
+            lat.spins.copy_(torch.from_numpy(s0))
+            lat.times.copy_(torch.from_numpy(t0))
+            lat.counts.copy_(torch.from_numpy(n0.view(np.int32)))
+            lat.resume(0.0)
+            lat.advance(T)
+            st = lat.stats()
+            assert_same_state(lat.read(), (s, t, n), str(tuning))
+            lat.close()
+            # the first launch's scan found about half the cells enabled, more
+            # than a list holds
+            assert st["launches"] >= 2
+        return
     s, t, n, ev, fl = oracle.simulate(params, params["T"])
     for tuning in tunings:
         say(f"compiled pitch {tuning} case {params['L']} rate {params['rate']}")
