@@ -90,11 +90,12 @@ def measured_traffic(workload: str, tuning: dict):
         doc = json.load(f)
     if doc.get("kernel_source_sha256") != kernel_source_digest():
         return None
-    prof = doc.get("tuning", {})
-    if any(list(prof.get(k, [])) != list(tuning.get(k, [])) for k in ("tile", "ghost")) or \
-            prof.get("block") != tuning.get("block"):
-        return None
-    return doc["hbm_bytes_per_launch"]
+    for entry in doc.get("entries", []):
+        prof = entry.get("tuning", {})
+        if all(list(prof.get(k, [])) == list(tuning.get(k, [])) for k in ("tile", "ghost")) and \
+                prof.get("block") == tuning.get("block"):
+            return entry["hbm_bytes_per_launch"]
+    return None
 
 
 def copy_calibration(nbytes: int = 1 << 31) -> None:
