@@ -201,6 +201,23 @@ def test_compiled_pitch_regions_match_oracle(torch, params, tunings):
         assert st["events"] == ev and st["flips"] == fl
 
 
+def test_flip_counts_at_255_rounds(torch):
+    """A visit's flip counts take one byte: at beta = 0 every Metropolis arrival
+    flips, and a 1D region with 300 ghost cells lets its middle cells apply many
+    arrivals (all flips) in one visit of up to 255 rounds (a larger max_sweeps
+    runs as 255)."""
+    params = workloads.lattice(1, (2000,), 0.0, "metropolis", seed=91, T=700.0)
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    assert fl == ev                      # every arrival flipped
+    for tuning in (dict(tile=(64,), ghost=(300,), max_sweeps=1000, block=256),
+                   dict(tile=(64,), ghost=(300,), max_sweeps=255, block=256)):
+        say(f"255 rounds {tuning}")
+        gs, gt, gn, st = gpu_run(params, params["T"], tuning=tuning)
+        assert_same_state((gs, gt, gn), (s, t, n), str(tuning))
+        assert st["events"] == ev and st["flips"] == fl
+        assert st["sweeps"] / st["visits"] > 50     # visits ran long
+
+
 def test_chunked_advance(torch):
     params = workloads.lattice(2, (150, 97), 0.42, "metropolis", h=-0.07, seed=21, T=30.0)
     s, t, n, ev, fl = oracle.simulate(params, 30.0)
