@@ -192,6 +192,18 @@ def test_compiled_pitch_regions_match_oracle(torch, params, tunings):
             # the first launch's scan found about half the cells enabled, more
             # than a list holds
             assert st["launches"] >= 2
+        # the same state through the persistent batch kernel
+        say(f"checkerboard case {params['L']} through a batch")
+        lat = aca.Lattice(params)
+        lat.spins.copy_(torch.from_numpy(s0))
+        lat.times.copy_(torch.from_numpy(t0))
+        lat.counts.copy_(torch.from_numpy(n0.view(np.int32)))
+        lat.resume(0.0)
+        b = aca.Batch(1)
+        b.advance([lat], [T])
+        b.close()
+        assert_same_state(lat.read(), (s, t, n), "batch")
+        lat.close()
         return
     s, t, n, ev, fl = oracle.simulate(params, params["T"])
     for tuning in tunings:
