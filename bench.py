@@ -597,10 +597,11 @@ def main() -> int:
         lat.init()
         # a slice should span several launches: a slice's last launch is a
         # partial one that costs nearly a whole launch, which would favour
-        # the candidates with fewer rounds per visit in short slices; five
-        # candidates of T/6 each leave a sixth of the horizon for the finish
+        # the candidates with fewer rounds per visit in short slices.  On a
+        # large 2D lattice five strong candidates of T/6 each leave a sixth of
+        # the horizon for the finish; elsewhere the library's set, T/20 each
         cands = None
-        if params["dim"] == 2:
+        if params["dim"] == 2 and min(params["L"]) >= 1024:
             cands = [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40),
                      dict(tile=(64, 60), ghost=(5, 5), max_sweeps=32),
                      dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32),
