@@ -194,6 +194,41 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
     }
 }
 
+// A lattice too small to give the compute units many default regions runs
+// few workgroups per launch, so its launches are short and latency-bound:
+// smaller tiles (more workgroups), wider ghosts and longer visits (a region
+// moves further per launch, so fewer launches) pay more than the larger
+// surface costs.  Applied to automatic knobs of a single lattice only (a
+// batch fills the device with many lattices and keeps the defaults), and
+// only where every side leaves room for the wider ghost.
+void small_lattice_tuning(const aca_params &p, aca_tuning *t)
+{
+    if (p.range > 1) return;
+    uint64_t n = 1;
+    int lmin = p.L[0];
+    for (int d = 0; d < p.dim; ++d) {
+        n *= (uint64_t)p.L[d];
+        lmin = std::min(lmin, p.L[d]);
+    }
+    if (p.dim == 2 && n <= 512ull * 512 && lmin >= 32) {
+        for (int d = 0; d < 2; ++d) {
+            t->tile[d] = std::min(40, (p.L[d] + 2) / 3);
+            t->ghost[d] = 8;
+        }
+        t->max_sweeps = 64;
+    } else if (p.dim == 3 && n <= 128ull * 128 * 128 && lmin >= 16) {
+        for (int d = 0; d < 3; ++d) {
+            t->tile[d] = std::min(16, (p.L[d] + 2) / 3);
+            t->ghost[d] = 2;
+        }
+        t->max_sweeps = 16;
+    } else if (p.dim == 1 && n <= 32768 && lmin >= 1024) {
+        t->tile[0] = std::max(256, (p.L[0] + 3) / 4);
+        t->ghost[0] = 64;
+        t->max_sweeps = 128;
+    }
+}
+
 int tune_candidates(int dim, aca_tuning *out)
 {
     // tile sides, ghost width, worklist rounds per visit
@@ -245,6 +280,7 @@ aca_status make_plan(const aca_lattice *lat, double T, Plan *plan)
     memset(&t, 0, sizeof t);
     t.ghost[0] = t.ghost[1] = t.ghost[2] = -1;
     auto_tuning(p, &t);
+    small_lattice_tuning(p, &t);
     for (int d = 0; d < 3; ++d) {
         if (lat->tun.tile[d] > 0) t.tile[d] = lat->tun.tile[d];
         if (lat->tun.ghost[d] >= 0) t.ghost[d] = lat->tun.ghost[d];
