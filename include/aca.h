@@ -84,6 +84,10 @@ typedef struct aca_params {
 
 /* Schedule knobs; they never change results (partition invariance argued
  * for Fig. 3.4), only speed.  struct_size must be sizeof(aca_tuning).
+ * Automatic values depend on the dimension and, for a single lattice too
+ * small to give the device many default regions, on its size (smaller tiles,
+ * wider ghosts, more rounds); batch and server members take the defaults of
+ * their dimension. */
  *  tile[d]    own cells of a workgroup tile along d (0 = automatic)
  *  ghost[d]   extra cells simulated on each side and discarded (-1 = auto)
  *  max_sweeps worklist rounds of a tile per visit (0 = automatic; larger
