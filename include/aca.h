@@ -87,7 +87,7 @@ typedef struct aca_params {
  * Automatic values depend on the dimension and, for a single lattice too
  * small to give the device many default regions, on its size (smaller tiles,
  * wider ghosts, more rounds); batch and server members take the defaults of
- * their dimension. */
+ * their dimension.
  *  tile[d]    own cells of a workgroup tile along d (0 = automatic)
  *  ghost[d]   extra cells simulated on each side and discarded (-1 = auto)
  *  max_sweeps worklist rounds of a tile per visit (0 = automatic; larger
