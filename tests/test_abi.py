@@ -25,6 +25,24 @@ def test_header_declares_the_binding_surface():
     assert names == sorted(aca.EXPORTED)
 
 
+def test_header_is_plain_c():
+    """The boundary header compiles as C99 on its own, warnings as errors."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "use.c")
+        with open(src, "w") as f:
+            f.write('#include "aca.h"\nint main(void) { return (int)sizeof(aca_tuning) == 0; }\n')
+        r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                            "-fsyntax-only", "-I", os.path.join(ROOT, "include"), src],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
 def test_library_exports_every_declared_symbol():
     lib = aca.load()
     for name in declared_functions():
