@@ -602,11 +602,11 @@ def main() -> int:
         # the horizon for the finish; elsewhere the library's set, T/20 each
         cands = None
         if params["dim"] == 2 and min(params["L"]) >= 1024:
-            cands = [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40),
+            cands = [dict(tile=(72, 54), ghost=(5, 5), max_sweeps=40),
+                     dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40),
+                     dict(tile=(72, 54), ghost=(5, 5), max_sweeps=32),
                      dict(tile=(64, 60), ghost=(5, 5), max_sweeps=32),
-                     dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32),
-                     dict(tile=(62, 54), ghost=(5, 5), max_sweeps=32),
-                     dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32)]
+                     dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32)]
         tune = lat.tune(max(T / (6.0 if cands else 20.0), 1e-3), cands)
         lat.advance(T)
         log(f"autotuned: {tune['tuning']} (rates per ms "

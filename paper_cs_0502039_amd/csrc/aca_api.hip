@@ -178,9 +178,9 @@ void auto_tuning(const aca_params &p, aca_tuning *t)
         t->tile[0] = 8192; t->ghost[0] = 64;
         t->max_sweeps = 512; t->block = 256;
     } else if (p.dim == 2) {
-        // a 76 x 72 box (78 KB of LDS: two workgroups per CU); 5 ghost cells
+        // an 84 x 66 box (79 KB of LDS: two workgroups per CU); 5 ghost cells
         // let a visit move its region one layer further than 4 at the same box
-        t->tile[0] = 64; t->tile[1] = 60;
+        t->tile[0] = 72; t->tile[1] = 54;
         t->ghost[0] = 5; t->ghost[1] = 5;
         t->max_sweeps = 40; t->block = 512;
     } else {
@@ -234,8 +234,8 @@ int tune_candidates(int dim, aca_tuning *out)
     // tile sides, ghost width, worklist rounds per visit
     static const int c1[][3] = {{8192, 64, 512}, {4096, 32, 256}, {16384, 64, 1024},
                                 {8192, 128, 1024}, {2048, 16, 128}};
-    static const int c2[][5] = {{64, 60, 5, 40, 0}, {64, 60, 5, 32, 0}, {64, 52, 5, 32, 0},
-                                {62, 54, 5, 32, 0}, {64, 56, 4, 32, 0}, {32, 32, 2, 16, 0}};
+    static const int c2[][5] = {{72, 54, 5, 40, 0}, {64, 60, 5, 40, 0}, {72, 54, 5, 32, 0},
+                                {64, 60, 5, 32, 0}, {64, 52, 5, 32, 0}, {32, 32, 2, 16, 0}};
     // tile sides, ghost, rounds, threads
     static const int c3[][6] = {{20, 20, 16, 1, 12, 1024}, {20, 20, 16, 1, 16, 1024},
                                 {20, 20, 14, 1, 12, 1024}, {18, 18, 14, 2, 16, 1024},

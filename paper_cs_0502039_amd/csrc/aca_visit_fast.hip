@@ -70,10 +70,10 @@ const void *near_fn(int dim)
 }
 
 // Box pitches compiled as constants (own tile + 2 ghost + 2 ring cells a
-// side).  2D: 76 x 72 (the default 64 x 60 tile with 5 ghost cells), 76 x 64
-// (64 x 52 with 5) and 74 x 66 (64 x 56 with 4, or 62 x 54 with 5); 3D:
-// 24 x 24 x 20 (the default 20 x 20 x 16 tile with 1, or 18 x 18 x 14 with 2)
-// and 24 x 24 x 18 (20 x 20 x 14 with 1).
+// side).  2D: 84 x 66 (the default 72 x 54 tile with 5 ghost cells), 76 x 72
+// (64 x 60 with 5) and 76 x 64 (64 x 52 with 5); 3D: 24 x 24 x 20 (the
+// default 20 x 20 x 16 tile with 1, or 18 x 18 x 14 with 2) and 24 x 24 x 18
+// (20 x 20 x 14 with 1).
 template <int P0, int P1, int P2>
 struct CompiledPitch {
     static constexpr int dim = P2 > 1 ? 3 : 2;
@@ -87,9 +87,9 @@ struct CompiledPitch {
                     : (const void *)visit_fast_kernel<dim, false, 1, false, false, P0, P1, P2>;
     }
 };
-using Pitch2a = CompiledPitch<64 + 2 * 5 + 2, 60 + 2 * 5 + 2, 0>;
-using Pitch2b = CompiledPitch<64 + 2 * 5 + 2, 52 + 2 * 5 + 2, 0>;
-using Pitch2c = CompiledPitch<64 + 2 * 4 + 2, 56 + 2 * 4 + 2, 0>;
+using Pitch2a = CompiledPitch<72 + 2 * 5 + 2, 54 + 2 * 5 + 2, 0>;
+using Pitch2b = CompiledPitch<64 + 2 * 5 + 2, 60 + 2 * 5 + 2, 0>;
+using Pitch2c = CompiledPitch<64 + 2 * 5 + 2, 52 + 2 * 5 + 2, 0>;
 using Pitch3a = CompiledPitch<20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 16 + 2 * 1 + 2>;
 using Pitch3b = CompiledPitch<20 + 2 * 1 + 2, 20 + 2 * 1 + 2, 14 + 2 * 1 + 2>;
 

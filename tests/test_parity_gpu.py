@@ -136,14 +136,17 @@ def test_result_independent_of_tiling(torch, params, tuning):
 # wide with a ragged last tile along every direction and rate 1 and 0.37.
 COMPILED_PITCH_CASES = [
     (workloads.lattice(2, (150, 131), 0.41, seed=81, T=6.0),
-     [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512),
+     [dict(tile=(72, 54), ghost=(5, 5), max_sweeps=40, block=512),
+      dict(tile=(70, 52), ghost=(6, 6), max_sweeps=40, block=512),
+      dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512),
       dict(tile=(62, 58), ghost=(6, 6), max_sweeps=40, block=512),
       dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
       dict(tile=(62, 50), ghost=(6, 6), max_sweeps=40, block=512),
       dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512),
       dict(tile=(62, 54), ghost=(5, 5), max_sweeps=16, block=512)]),
     (workloads.lattice(2, (131, 140), 0.3, "metropolis", h=0.2, seed=82, T=5.0, rate=0.37),
-     [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512),
+     [dict(tile=(72, 54), ghost=(5, 5), max_sweeps=40, block=512),
+      dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512),
       dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
       dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512)]),
     (workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", h=0.1, init="plus", seed=83, T=4.0),
@@ -159,7 +162,7 @@ COMPILED_PITCH_CASES = [
     # holds half the simulated cells, past the list capacity, and the cells
     # that do not fit wait for the next visit
     (dict(workloads.lattice(2, (150, 131), 0.41, seed=85, T=6.0), checkerboard=True),
-     [dict(tile=(64, 60), ghost=(5, 5), max_sweeps=40, block=512)]),
+     [dict(tile=(72, 54), ghost=(5, 5), max_sweeps=40, block=512)]),
     (dict(workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", seed=86, T=3.0), checkerboard=True),
      [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
 ]
