@@ -70,3 +70,31 @@ def test_random_draw_matches_oracle(torch, i):
     assert np.array_equal(gt.view(np.uint64), t.view(np.uint64)), "times"
     assert np.array_equal(gn, n), "counts"
     assert st["events"] == ev and st["flips"] == fl
+
+
+N_AUTO = 24
+
+
+def draw_auto(i):
+    """A lattice of each dimension's larger sizes under the automatic schedule
+    (which switches to smaller tiles and wider ghosts for small lattices)."""
+    params, _ = draw(i)
+    rng = np.random.default_rng(7000 + i)
+    dim = params["dim"]
+    hi = {1: 30000, 2: 600, 3: 140}[dim]
+    L = [int(rng.integers(max(2, hi // 8), hi + 1)) for _ in range(dim)]
+    n = int(np.prod(L))
+    T = float(min(20.0, 2e6 / (n * params["rate"])) * rng.uniform(0.3, 1.0))
+    return dict(params, L=L, T=T)
+
+
+@pytest.mark.parametrize("i", range(N_AUTO))
+def test_random_draw_automatic_schedule(torch, i):
+    params = draw_auto(i)
+    print(f"auto draw {i}: {params}", file=sys.stderr, flush=True)
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    gs, gt, gn, st = aca.simulate(params, params["T"])
+    assert np.array_equal(gs, s), "spins"
+    assert np.array_equal(gt.view(np.uint64), t.view(np.uint64)), "times"
+    assert np.array_equal(gn, n), "counts"
+    assert st["events"] == ev and st["flips"] == fl
