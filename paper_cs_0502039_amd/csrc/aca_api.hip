@@ -235,12 +235,12 @@ int tune_candidates(int dim, aca_tuning *out)
     static const int c1[][3] = {{8192, 64, 512}, {4096, 32, 256}, {16384, 64, 1024},
                                 {8192, 128, 1024}, {2048, 16, 128}};
     static const int c2[][5] = {{72, 54, 5, 40, 0}, {64, 60, 5, 40, 0}, {72, 54, 5, 32, 0},
-                                {64, 60, 5, 32, 0}, {64, 52, 5, 32, 0}, {32, 32, 2, 16, 0}};
+                                {64, 60, 5, 32, 0}, {64, 52, 5, 32, 0}, {40, 40, 8, 64, 0}};
     // tile sides, ghost, rounds, threads
     static const int c3[][6] = {{20, 20, 16, 1, 12, 1024}, {20, 20, 16, 1, 16, 1024},
                                 {20, 20, 14, 1, 12, 1024}, {18, 18, 14, 2, 16, 1024},
-                                {20, 20, 12, 1, 12, 1024}, {16, 16, 8, 1, 12, 512},
-                                {20, 16, 12, 1, 16, 1024}, {8, 8, 8, 1, 8, 512}};
+                                {16, 16, 16, 2, 16, 1024}, {20, 20, 12, 1, 12, 1024},
+                                {16, 16, 8, 1, 12, 512}, {8, 8, 8, 1, 8, 512}};
     int n = 0;
     auto base = [&]() -> aca_tuning & {
         aca_tuning &t = out[n++];
