@@ -382,6 +382,12 @@ def bench_config(name: str, steps: int = 3) -> dict:
            "alu_frac": st["events"] / (st["kernel_ms"] / 1e3)
            / (VALU_LANE_OPS_PER_S / SLOTS_PER_EVENT),
            "tuning": lat.tuning()}
+    # measured HBM bytes per launch (profiles/traffic_<name>.json) while the
+    # kernels and the schedule match the counters, else None
+    traffic = measured_traffic(name, lat.tuning())
+    out["traffic_bytes_per_launch"] = traffic
+    if traffic is not None:
+        out["traffic_tb_per_s"] = traffic / (out["kernel_ms_per_launch"] / 1e3) / 1e12
     gold_path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
     if os.path.exists(gold_path):
         with open(gold_path) as f:
