@@ -58,15 +58,23 @@ const void *fast_fn()
     return (const void *)visit_fast_kernel<DIM, FRAMES, Q>;
 }
 
-template <bool UNIT, bool COUNT>
+template <bool UNIT, bool COUNT, bool FRAMES = false>
 const void *near_fn(int dim)
 {
     switch (dim) {
-    case 1: return (const void *)visit_fast_kernel<1, false, 1, UNIT, COUNT>;
-    case 2: return (const void *)visit_fast_kernel<2, false, 1, UNIT, COUNT>;
-    case 3: return (const void *)visit_fast_kernel<3, false, 1, UNIT, COUNT>;
+    case 1: return (const void *)visit_fast_kernel<1, FRAMES, 1, UNIT, COUNT>;
+    case 2: return (const void *)visit_fast_kernel<2, FRAMES, 1, UNIT, COUNT>;
+    case 3: return (const void *)visit_fast_kernel<3, FRAMES, 1, UNIT, COUNT>;
     default: return nullptr;
     }
+}
+
+// The nearest-neighbour visit that writes output frames: unit-rate and
+// uncounted instantiations too (the frame capture adds registers of its own).
+const void *near_frames_kernel(int dim, bool unit, bool count)
+{
+    if (count) return unit ? near_fn<true, true, true>(dim) : near_fn<false, true, true>(dim);
+    return unit ? near_fn<true, false, true>(dim) : near_fn<false, false, true>(dim);
 }
 
 // Box pitches compiled as constants (own tile + 2 ghost + 2 ring cells a
@@ -176,7 +184,9 @@ hipError_t launch_visit_fast(int dim, const VisitArgs &a, int block, size_t lds,
     region::box_pitch(a, dim, pitch);
     const void *fn = (q == 1 && !a.frames)
                          ? near_fast_kernel(dim, a.unit_rate != 0, a.count_efficiency != 0, pitch)
-                         : fast_kernel(dim, q, a.frames != nullptr);
+                         : (q == 1 ? near_frames_kernel(dim, a.unit_rate != 0,
+                                                        a.count_efficiency != 0)
+                                   : fast_kernel(dim, q, a.frames != nullptr));
     if (!fn) return hipErrorInvalidValue;
     void *args[] = {const_cast<VisitArgs *>(&a)};
     return hipLaunchKernel(fn, dim3(tiles), dim3(block), args, lds, stream);
@@ -193,6 +203,13 @@ hipError_t set_visit_fast_lds_limit(size_t bytes)
                     hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                 if (e != hipSuccess) return e;
             }
+    for (int dim = 1; dim <= 3; ++dim)
+        for (int v = 0; v < 4; ++v) {
+            const hipError_t e = hipFuncSetAttribute(near_frames_kernel(dim, v & 1, v & 2),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)bytes);
+            if (e != hipSuccess) return e;
+        }
     for (int dim = 1; dim <= 3; ++dim)
         for (int v = 0; v < 4; ++v) {
             const hipError_t e = hipFuncSetAttribute(near_fast_kernel(dim, v & 1, v & 2),

@@ -406,6 +406,7 @@ FRAME_CASES = [
     workloads.lattice(2, (37, 23), 0.3, "metropolis", h=0.2, seed=62, T=7.0),   # one region
     workloads.lattice(3, (40, 33, 21), 0.2, "metropolis", h=0.1, init="plus", seed=63, T=4.0),
     workloads.lattice(1, (5000,), 0.5, seed=64, T=6.0),
+    workloads.lattice(2, (160, 140), 0.44, seed=65, T=8.0, rate=0.37),   # rate != 1
 ]
 
 
