@@ -946,10 +946,11 @@ __device__ __forceinline__ RegionTally visit_region(const VisitArgs &a, const Sn
     // cells and reads all their input keys, before it issues any merge atomic
     // (reads, stores and atomics complete in order on one counter, so a read
     // issued after atomics would wait for them); the indices stay in registers
-    // for the second pass.  For nearest neighbours a step covers a whole
-    // region at the default tiles: 12 cells per thread in 1D and 2D (4608
-    // simulated cells for 512 threads), 8 in 3D (6776 for 1024 threads; fewer
-    // registers held measure faster there).
+    // for the second pass.  For nearest neighbours a thread takes 12 cells
+    // per step in 1D and 2D (6144 per step for 512 threads, against 5248
+    // simulated cells of a default 2D region) and 8 in 3D (two steps of 768
+    // threads for a default region's 8712; fewer registers held measure
+    // faster there).
     constexpr int UM = Q == 1 ? (DIM > 2 ? 8 : 12) : 4;   // a wider reach has no registers to spare
     bool live = false;
     for (int j0 = tid; j0 < nin; j0 += UM * nthreads) {

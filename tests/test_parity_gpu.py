@@ -150,12 +150,12 @@ COMPILED_PITCH_CASES = [
       dict(tile=(64, 52), ghost=(5, 5), max_sweeps=32, block=512),
       dict(tile=(64, 56), ghost=(4, 4), max_sweeps=32, block=512)]),
     (workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", h=0.1, init="plus", seed=83, T=4.0),
-     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=768),
       dict(tile=(18, 18, 14), ghost=(2, 2, 2), max_sweeps=16, block=1024),
-      dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024),
-      dict(tile=(18, 18, 12), ghost=(2, 2, 2), max_sweeps=16, block=1024)]),
+      dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=768),
+      dict(tile=(18, 18, 12), ghost=(2, 2, 2), max_sweeps=16, block=512)]),
     (workloads.lattice(3, (45, 41, 35), 0.2, "glauber", seed=84, T=3.0, rate=0.37),
-     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024),
+     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=768),
       dict(tile=(20, 20, 14), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
     # a state with every cell enabled at once where its neighbours' times are
     # larger (a checkerboard of early and late times): the first scan's list
@@ -164,7 +164,7 @@ COMPILED_PITCH_CASES = [
     (dict(workloads.lattice(2, (150, 131), 0.41, seed=85, T=6.0), checkerboard=True),
      [dict(tile=(72, 54), ghost=(5, 5), max_sweeps=40, block=512)]),
     (dict(workloads.lattice(3, (47, 44, 37), 0.22, "metropolis", seed=86, T=3.0), checkerboard=True),
-     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=1024)]),
+     [dict(tile=(20, 20, 16), ghost=(1, 1, 1), max_sweeps=12, block=768)]),
 ]
 
 

@@ -51,7 +51,7 @@ def draw(i):
     ghost = [int(rng.integers(0, 6)) for _ in range(dim)] + [0] * (3 - dim)
     tuning = dict(tile=tuple(tile), ghost=tuple(ghost),
                   max_sweeps=int(rng.choice([1, 2, 5, 16, 64, 1000])),
-                  block=int(rng.choice([64, 128, 256, 512, 1024])))
+                  block=int(rng.choice([64, 128, 256, 512, 768, 1024])))
     return params, tuning
 
 
