@@ -301,7 +301,7 @@ ACA_EXPORT aca_status aca_batch_get_tuning(const aca_batch *b, int32_t dim, aca_
     }
     if (u.max_sweeps > 0) t.max_sweeps = u.max_sweeps;
     t.struct_size = sizeof t;
-    t.block = 0;     // chosen per launch from the regions' LDS (512 or 1024)
+    t.block = 0;     // the persistent kernel always runs 512 threads per workgroup
     *out = t;
     return ACA_OK;
 }
