@@ -250,10 +250,12 @@ __host__ __device__ inline FastPlan fast_plan(const VisitArgs &a, int dim, const
     p.tmin_off = p.ctr_off + 64;                                // uint64 least owned time
     p.ball_off = p.tmin_off + 16;                               // int off[32], step[32]
     p.tab_off = p.ball_off + (ring > 1 ? 256 : 0);              // uint32 tx, ty, tz
-    // uint64 ts[boxp] with a guard of 2*pitch[0] words on both sides: the
-    // stencil's two-step loads around a cell on the first or last simulated
-    // layer may reach one layer beyond the box (those values are never used)
-    const size_t guard = 2 * (size_t)pitch[0];
+    // uint64 ts[boxp] with a guard on both sides: the stencil's two-step
+    // loads around a cell on the first or last simulated layer may reach one
+    // layer beyond the box (those values are never used).  A layer is a row
+    // of pitch[0] cells in 2D and 3D and a single cell in 1D, whose box is
+    // one row: a guard of two rows there would triple its LDS.
+    const size_t guard = 2 * (size_t)(dim == 1 ? 1 : pitch[0]);
     p.ts_off = (p.tab_off + 4 * (size_t)(pitch[0] + pitch[1] + pitch[2]) + 7) & ~(size_t)7;
     p.ts_off += 8 * guard;
     p.n_off = p.ts_off + 8 * (boxp + guard);                    // uint32 n[boxp] | claim

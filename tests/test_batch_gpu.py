@@ -185,6 +185,24 @@ def test_batch_equals_single_lattice_path(torch):
         assert np.array_equal(g[2][cells], nc)
 
 
+def test_batch_takes_long_1d_lattices(torch):
+    """1D members whose tiles are thousands of cells long (a line cut into two
+    tiles of about 8000) fit a region's LDS and match the oracle, next to 2D
+    and 3D members."""
+    cases = [workloads.lattice(1, (16264,), 0.45, seed=16, T=15.0),
+             workloads.lattice(1, (20000,), 0.4, "metropolis", h=0.1, seed=19, T=12.0,
+                               rate=0.37),
+             workloads.lattice(2, (40, 33), 0.4, seed=17, T=10.0),
+             workloads.lattice(3, (12, 10, 9), 0.2, "metropolis", seed=20, T=6.0)]
+    say("batch with long 1D lattices")
+    got, stats, bstats = run_batch(cases)
+    assert bstats["finished"] == len(cases)
+    for p, g, st in zip(cases, got, stats):
+        want, ev, fl = oracle_state(p)
+        assert_same_state(g, want, f"{p['dim']}D L={p['L']}")
+        assert st["events"] == ev and st["flips"] == fl
+
+
 def test_batch_state_errors(torch):
     p = workloads.lattice(2, (16, 16), 0.3, T=3.0)
     lat = aca.Lattice(p).init()

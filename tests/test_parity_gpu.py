@@ -233,6 +233,21 @@ def test_flip_counts_at_255_rounds(torch):
         assert st["sweeps"] / st["visits"] > 50     # visits ran long
 
 
+@pytest.mark.parametrize("params", [
+    workloads.lattice(1, (20000,), 0.4, seed=13, T=60.0),
+    workloads.lattice(1, (40000,), 0.3, "metropolis", h=0.1, seed=18, T=8.0, rate=0.37),
+], ids=["1d-20000", "1d-40000"])
+def test_long_1d_regions_match_oracle(torch, params):
+    """1D regions of several thousand cells (the automatic 1D tiles: a quarter
+    of a small line, 8192 cells beyond) fit the LDS, since a 1D box needs a
+    guard of one cell beyond each end, and match the oracle."""
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    say(f"long 1D regions {params['L']}")
+    gs, gt, gn, st = gpu_run(params, params["T"])
+    assert_same_state((gs, gt, gn), (s, t, n), str(params["L"]))
+    assert st["events"] == ev and st["flips"] == fl
+
+
 def test_chunked_advance(torch):
     params = workloads.lattice(2, (150, 97), 0.42, "metropolis", h=-0.07, seed=21, T=30.0)
     s, t, n, ev, fl = oracle.simulate(params, 30.0)
