@@ -248,6 +248,30 @@ def test_long_1d_regions_match_oracle(torch, params):
     assert st["events"] == ev and st["flips"] == fl
 
 
+def test_size_dependent_schedules_match_oracle(torch):
+    """The automatic schedule of a single lattice depends on its size (small
+    and mid-size 2D and 3D lattices, 1D lines); each choice must still give the
+    oracle's trajectory."""
+    cases = [(workloads.lattice(2, (600, 500), 0.44, seed=101, T=3.0), (56, 48)),
+             (workloads.lattice(2, (300, 200), 0.3, "metropolis", h=0.1, seed=102, T=6.0,
+                                rate=0.37), (40, 40)),
+             (workloads.lattice(3, (40, 36, 33), 0.22, "metropolis", h=0.1, seed=103, T=4.0),
+              (14, 12, 11)),
+             (workloads.lattice(3, (100, 90, 80), 0.22, "metropolis", init="plus", seed=104,
+                                T=1.0), (16, 16, 16)),
+             (workloads.lattice(1, (70000,), 0.5, seed=105, T=10.0), (274,))]
+    for params, tile in cases:
+        say(f"size-dependent schedule {params['L']}")
+        s, t, n, ev, fl = oracle.simulate(params, params["T"])
+        lat = aca.Lattice(params)
+        assert tuple(lat.tuning()["tile"][:params["dim"]]) == tile
+        lat.init().advance(params["T"])
+        st = lat.stats()
+        assert_same_state(lat.read(), (s, t, n), str(params["L"]))
+        assert st["events"] == ev and st["flips"] == fl
+        lat.close()
+
+
 def test_chunked_advance(torch):
     params = workloads.lattice(2, (150, 97), 0.42, "metropolis", h=-0.07, seed=21, T=30.0)
     s, t, n, ev, fl = oracle.simulate(params, 30.0)
