@@ -272,6 +272,32 @@ def test_size_dependent_schedules_match_oracle(torch):
         lat.close()
 
 
+BOUNDARY_CASES = [
+    (workloads.lattice(2, (512, 512), 0.44, seed=111, T=2.0), (40, 40)),
+    (workloads.lattice(2, (513, 512), 0.44, seed=112, T=2.0), (56, 48)),
+    (workloads.lattice(2, (1537, 1536), 0.44, seed=113, T=0.25), (72, 54)),
+    (workloads.lattice(3, (65, 64, 64), 0.22, "metropolis", h=0.1, seed=114, T=2.0), (16, 16, 16)),
+    (workloads.lattice(3, (129, 128, 128), 0.22, "metropolis", h=0.1, seed=115, T=0.25),
+     (20, 20, 16)),
+    (workloads.lattice(1, (257,), 0.5, seed=116, T=30.0), (129,)),
+    (workloads.lattice(1, (65537,), 0.5, seed=117, T=9.0), (257,)),
+]
+
+
+@pytest.mark.parametrize("params,tile", BOUNDARY_CASES,
+                         ids=lambda v: "x".join(map(str, v["L"])) if isinstance(v, dict) else "")
+def test_schedule_rule_boundaries_match_oracle(torch, params, tile):
+    """Lattices on either side of a size threshold of the automatic schedule."""
+    s, t, n, ev, fl = oracle.simulate(params, params["T"])
+    lat = aca.Lattice(params)
+    assert tuple(lat.tuning()["tile"][:params["dim"]]) == tile
+    lat.init().advance(params["T"])
+    st = lat.stats()
+    assert_same_state(lat.read(), (s, t, n), str(params["L"]))
+    assert st["events"] == ev and st["flips"] == fl
+    lat.close()
+
+
 def test_chunked_advance(torch):
     params = workloads.lattice(2, (150, 97), 0.42, "metropolis", h=-0.07, seed=21, T=30.0)
     s, t, n, ev, fl = oracle.simulate(params, 30.0)
